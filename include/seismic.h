@@ -1,0 +1,181 @@
+/*
+ * seismic.h - C ABI of the MI355X (gfx950) Seismic query-processing library.
+ *
+ * Seismic (Bruch, Nardini, Rulli, Venturini, "Efficient Sketching and Nearest
+ * Neighbor Search Algorithms for Sparse Vector Sets") answers sparse maximum
+ * inner product search (Definition "Sparse MIPS", Section 1.1) approximately
+ * with an inverted index whose lists are truncated (Set alpha-MSS, Section
+ * 3.4), clustered into blocks (Section 4.1.2) and summarized by u8-quantized
+ * gamma-mass summaries (Section 4.1.3); queries are answered by Algorithm 2
+ * (Section 4.5).  This library builds that index on the host, keeps it in
+ * HBM and answers batches of queries with HIP kernels.
+ *
+ * Conventions
+ *   - Every function returns 0 (SEISMIC_OK) or a negative SEISMIC_E* code;
+ *     seismic_last_error() returns a thread-local message for the last
+ *     failure.  No C++ exception crosses this boundary.
+ *   - Sparse rows use CSR: row_ptr u64[n_rows + 1] (row_ptr[0] == 0,
+ *     row_ptr[n_rows] == nnz) and one 32-bit word per nonzero: bits 0..15
+ *     hold the coordinate (term id < dim), bits 16..31 the IEEE binary16
+ *     value.  Terms are strictly ascending inside a row; values are finite
+ *     and positive.
+ *   - "device" pointers are HIP device memory on the index's device;
+ *     "host" pointers are ordinary host memory.  Output buffers are always
+ *     caller-owned.  Handles are library-owned and released by *_free.
+ *   - stream is a hipStream_t (NULL = the legacy default stream).  Search
+ *     and exact search are asynchronous on that stream.
+ *   - Numerics: products of fp16 values are exact in fp32; sums are taken in
+ *     fp64 and rounded once to fp32.  For values in [2^-6, 2^6] every sum is
+ *     exact, so scores do not depend on summation order.
+ */
+#ifndef SEISMIC_H
+#define SEISMIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SEISMIC_OK = 0,
+    SEISMIC_EINVAL = -1,  /* invalid argument or input */
+    SEISMIC_ENOMEM = -2,  /* host or device allocation failed, or a capacity was exceeded */
+    SEISMIC_EHIP = -3,    /* a HIP runtime call failed */
+    SEISMIC_EIO = -4,     /* file could not be read or written */
+    SEISMIC_EFORMAT = -5, /* malformed or truncated serialized index */
+    SEISMIC_ESTATE = -6   /* object not in the required state (e.g. index not on a device) */
+};
+
+typedef struct seismic_index seismic_index;         /* immutable after build/load */
+typedef struct seismic_workspace seismic_workspace; /* per-stream scratch for search */
+
+/* A CSR matrix of sparse rows (see Conventions).  on_device = 0: host
+   pointers; 1: device pointers on the index's device. */
+typedef struct {
+    uint64_t n_rows;
+    uint64_t nnz;
+    uint32_t dim;
+    uint32_t on_device;
+    const uint64_t* row_ptr;
+    const uint32_t* words;
+} seismic_csr;
+
+/* Index-build hyperparameters (Algorithm "Indexing with Seismic", Section
+   4.4), fixed-cap form: lambda = largest values kept per coordinate (Set
+   alpha-MSS with a fixed cap); beta = number of blocks of a list holding
+   lambda entries (a list of n entries gets max(1, ceil(beta * n / lambda))
+   blocks, empty clusters dropped); gamma = mass fraction kept by each
+   block summary (gamma-MSS of the max vector, "summary" equation);
+   seed keys the centroid sampling; n_threads = host threads (0 = all). */
+typedef struct {
+    uint32_t lambda;
+    uint32_t beta;
+    double gamma;
+    uint64_t seed;
+    int32_t n_threads;
+    int32_t reserved;
+} seismic_build_params;
+
+/* Search parameters (inputs of Algorithm 2): k results; query_cut = number
+   of largest query coordinates whose lists are visited (0 = all of them),
+   the fixed-size stand-in for the alpha_q-MSS of the query; heap_factor > 0:
+   a block whose summary score r satisfies r * heap_factor < heap.min (with a
+   full heap) is skipped and ends its list; +INFINITY disables pruning. */
+typedef struct {
+    uint32_t k;
+    uint32_t query_cut;
+    float heap_factor;
+    uint32_t flags; /* must be 0 */
+} seismic_search_params;
+
+/* Optional per-query statistics (device pointers; each may be NULL).
+   prefix[q * prefix_stride + i] = number of blocks evaluated in the i-th
+   visited list of query q (0 beyond the cut); counters[q * 8 + j]:
+   0 summary entries of the visited lists, 1 blocks of the visited lists,
+   2 blocks evaluated, 3 documents in evaluated blocks, 4 nonzeros of those
+   documents, 5 prune tests made with a full heap, 6 status (0 = the query
+   row was valid, else a SEISMIC_QSTATUS_* bit set), 7 visited lists. */
+typedef struct {
+    uint16_t* prefix;
+    uint32_t prefix_stride;
+    uint32_t reserved;
+    uint64_t* counters;
+} seismic_stats;
+
+#define SEISMIC_QSTATUS_TERM_RANGE 1u /* a term id >= dim was ignored */
+#define SEISMIC_QSTATUS_UNSORTED 2u   /* terms not strictly ascending */
+#define SEISMIC_QSTATUS_TOO_LONG 4u   /* more than SEISMIC_MAX_QUERY_NNZ nonzeros: the rest were ignored */
+#define SEISMIC_QSTATUS_BAD_VALUE 8u  /* a value was not finite and positive */
+
+#define SEISMIC_MAX_QUERY_NNZ 1024
+#define SEISMIC_MAX_K 1024
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char* seismic_last_error(void);
+
+/* Build an index on the host from host-resident documents (on_device must
+   be 0).  Synchronous; the documents are copied (the forward index of
+   Section 4.2 is part of the index).  EINVAL on invalid rows or
+   parameters, ENOMEM on allocation failure. */
+int seismic_build_index(const seismic_csr* docs, const seismic_build_params* params, seismic_index** out);
+
+/* Serialized form (format version 1, little-endian): see DESIGN notes in
+   the source.  save writes a file; serialize writes into a caller buffer of
+   seismic_index_serialized_size() bytes.  EIO on write failure. */
+int seismic_index_serialized_size(const seismic_index* index, uint64_t* bytes);
+int seismic_index_serialize(const seismic_index* index, void* buf, uint64_t bytes);
+int seismic_index_save(const seismic_index* index, const char* path);
+
+/* Load a serialized index into host memory (EIO, EFORMAT on bad files). */
+int seismic_index_load(const char* path, seismic_index** out);
+
+/* out[0..7] = dim, n_docs, nnz, n_blocks, n_postings, n_summary entries,
+   lambda, beta; out[8] = largest number of blocks in one list; out[9] = 1
+   when the index is resident on a device. */
+int seismic_index_info(const seismic_index* index, uint64_t out[10]);
+
+/* Copy the index to HBM of HIP device `device` (synchronous).  Required
+   before search.  ENOMEM if it does not fit, EHIP on runtime errors. */
+int seismic_index_upload(seismic_index* index, int device);
+
+/* Release host and device memory of the index. */
+void seismic_index_free(seismic_index* index);
+
+/* Scratch for batches of up to max_queries queries with k <= max_k on the
+   index's device.  One workspace serves one stream at a time. */
+int seismic_workspace_create(const seismic_index* index, uint32_t max_queries, uint32_t max_k,
+                             seismic_workspace** out);
+void seismic_workspace_free(seismic_workspace* ws);
+
+/*
+ * Algorithm 2 (kappa = 0) for a batch of queries, asynchronously on stream.
+ * out_ids [n_queries * k] u32 and out_scores [n_queries * k] f32 are device
+ * buffers; each row is sorted by (score desc, id asc) and padded with
+ * (0xFFFFFFFF, -INFINITY).  Host-resident queries are validated (EINVAL)
+ * and copied through the workspace; device-resident queries are checked by
+ * the kernel, which never reads out of bounds and reports a per-query
+ * status in stats->counters.  EINVAL: bad parameters (k = 0 or > max_k,
+ * heap_factor <= 0 or NaN, flags != 0, batch larger than the workspace).
+ */
+int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, const seismic_csr* queries,
+                         const seismic_search_params* params, uint32_t* out_ids, float* out_scores,
+                         const seismic_stats* stats, void* stream);
+
+/*
+ * Exact top-k (Definition "Sparse MIPS") over the index's forward index:
+ * the k documents with the largest inner product, ties by id, documents with
+ * a zero score excluded, rows padded like seismic_search_batch.  The first
+ * call builds a full (untruncated) inverted index on the host and copies it
+ * to the device (about 6 bytes per nonzero; synchronous).  queries may be
+ * host or device resident (host: copied with a synchronous copy).
+ * k <= SEISMIC_MAX_K.
+ */
+int exact_topk(const seismic_index* index, const seismic_csr* queries, uint32_t k, uint32_t* out_ids,
+               float* out_scores, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEISMIC_H */

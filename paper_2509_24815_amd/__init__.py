@@ -1,0 +1,93 @@
+"""Seismic sparse-MIPS query processing on MI355X (gfx950).
+
+The product is ``libseismic.so`` (C ABI in ``include/seismic.h``); this
+package holds its HIP/C++ sources (``csrc/``), the build script and a thin
+Python binding (``binding``) plus a convenience wrapper (``Index``).
+"""
+from __future__ import annotations
+
+from . import binding
+from .binding import SeismicError
+
+__all__ = ["binding", "Index", "SeismicError"]
+
+
+class Index:
+    """Owning wrapper around a seismic_index handle."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+        self._ws = {}
+
+    @classmethod
+    def build(cls, docs, lam: int, beta: int, gamma: float, seed: int = 0, n_threads: int = 0) -> "Index":
+        return cls(binding.seismic_build_index(docs.row_ptr, docs.words, docs.dim, lam, beta, gamma, seed, n_threads))
+
+    @classmethod
+    def load(cls, path: str) -> "Index":
+        return cls(binding.seismic_index_load(path))
+
+    def save(self, path: str):
+        binding.seismic_index_save(self.handle, path)
+
+    def serialize(self):
+        return binding.seismic_index_serialize(self.handle)
+
+    def info(self) -> dict:
+        return binding.seismic_index_info(self.handle)
+
+    def upload(self, device: int = 0):
+        binding.seismic_index_upload(self.handle, device)
+
+    def workspace(self, max_queries: int, max_k: int) -> int:
+        key = (max_queries, max_k)
+        if key not in self._ws:
+            self._ws[key] = binding.seismic_workspace_create(self.handle, max_queries, max_k)
+        return self._ws[key]
+
+    def search(self, queries, k: int, query_cut: int, heap_factor: float, *, stats: bool = False,
+               prefix_stride: int | None = None, stream=None, ws=None):
+        """Batched search.  ``queries`` is a binding.Csr (host or device).
+        Returns torch tensors on the current device (ids, scores[, prefix,
+        counters])."""
+        import torch
+        nq = int(queries.n_rows)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        sc = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        prefix = counters = None
+        if stats:
+            stride = prefix_stride or max(1, query_cut if query_cut > 0 else binding.MAX_QUERY_NNZ)
+            prefix = torch.zeros((nq, stride), dtype=torch.int16, device=dev)
+            counters = torch.zeros((nq, 8), dtype=torch.int64, device=dev)
+        else:
+            stride = 0
+        w = ws if ws is not None else self.workspace(max(nq, 1), max(k, 1))
+        binding.seismic_search_batch(self.handle, w, queries, k, query_cut, heap_factor, ids, sc,
+                                     prefix, stride, counters, stream)
+        if stats:
+            return ids, sc, prefix, counters
+        return ids, sc
+
+    def exact(self, queries, k: int, stream=None):
+        import torch
+        nq = int(queries.n_rows)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        sc = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        binding.exact_topk(self.handle, queries, k, ids, sc, stream)
+        return ids, sc
+
+    def close(self):
+        for w in self._ws.values():
+            binding.seismic_workspace_free(w)
+        self._ws = {}
+        if self.handle:
+            binding.seismic_index_free(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

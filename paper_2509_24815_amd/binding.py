@@ -1,0 +1,193 @@
+"""Thin ctypes binding of libseismic.so.
+
+Functions carry the C names and only marshal arguments: host inputs are
+numpy arrays, device buffers are torch tensors (their data_ptr() is passed)
+and streams are torch.cuda streams.  Every step of the search runs in the
+library's HIP kernels; if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libseismic.so")
+
+OK, EINVAL, ENOMEM, EHIP, EIO, EFORMAT, ESTATE = 0, -1, -2, -3, -4, -5, -6
+MAX_QUERY_NNZ = 1024
+MAX_K = 1024
+COUNTER_NAMES = ("summary_entries", "blocks_in_lists", "blocks_evaluated", "docs_evaluated",
+                 "nnz_evaluated", "prune_tests", "status", "cut_len")
+
+_lib = None
+
+
+class SeismicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_uint64), ("nnz", ctypes.c_uint64), ("dim", ctypes.c_uint32),
+                ("on_device", ctypes.c_uint32), ("row_ptr", ctypes.c_void_p), ("words", ctypes.c_void_p)]
+
+
+class BuildParams(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_uint32), ("beta", ctypes.c_uint32), ("gamma", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("n_threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SearchParams(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("query_cut", ctypes.c_uint32), ("heap_factor", ctypes.c_float),
+                ("flags", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("prefix", ctypes.c_void_p), ("prefix_stride", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("counters", ctypes.c_void_p)]
+
+
+def load():
+    """Load libseismic.so (torch first, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "seismic_last_error": ([], ctypes.c_char_p),
+        "seismic_build_index": ([P(Csr), P(BuildParams), P(vp)], i32),
+        "seismic_index_serialized_size": ([vp, P(u64)], i32),
+        "seismic_index_serialize": ([vp, vp, u64], i32),
+        "seismic_index_save": ([vp, ctypes.c_char_p], i32),
+        "seismic_index_load": ([ctypes.c_char_p, P(vp)], i32),
+        "seismic_index_info": ([vp, vp], i32),
+        "seismic_index_upload": ([vp, i32], i32),
+        "seismic_index_free": ([vp], None),
+        "seismic_workspace_create": ([vp, u32, u32, P(vp)], i32),
+        "seismic_workspace_free": ([vp], None),
+        "seismic_search_batch": ([vp, vp, P(Csr), P(SearchParams), vp, vp, P(Stats), vp], i32),
+        "exact_topk": ([vp, P(Csr), u32, vp, vp, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise SeismicError(rc, load().seismic_last_error().decode())
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    return int(x.ctypes.data)
+
+
+def host_csr(row_ptr: np.ndarray, words: np.ndarray, dim: int) -> Csr:
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.uint64)
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    c = Csr(len(row_ptr) - 1, len(words), dim, 0, _ptr(row_ptr), _ptr(words) if len(words) else 0)
+    c._keep = (row_ptr, words)
+    return c
+
+
+def device_csr(row_ptr, words, dim: int) -> Csr:
+    """row_ptr (int64/uint64) and words (int32/uint32) torch tensors on the GPU."""
+    c = Csr(row_ptr.numel() - 1, words.numel(), dim, 1, _ptr(row_ptr), _ptr(words) if words.numel() else 0)
+    c._keep = (row_ptr, words)
+    return c
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+# ----------------------------------------------------------------- C names
+
+def seismic_build_index(row_ptr, words, dim, lam, beta, gamma, seed=0, n_threads=0) -> int:
+    lib = load()
+    csr = host_csr(row_ptr, words, dim)
+    p = BuildParams(lam, beta, gamma, seed, n_threads, 0)
+    h = ctypes.c_void_p()
+    _check(lib.seismic_build_index(ctypes.byref(csr), ctypes.byref(p), ctypes.byref(h)))
+    return h.value
+
+
+def seismic_index_serialize(handle) -> np.ndarray:
+    lib = load()
+    n = ctypes.c_uint64()
+    _check(lib.seismic_index_serialized_size(handle, ctypes.byref(n)))
+    buf = np.empty(n.value, dtype=np.uint8)
+    _check(lib.seismic_index_serialize(handle, _ptr(buf), n.value))
+    return buf
+
+
+def seismic_index_save(handle, path: str):
+    _check(load().seismic_index_save(handle, os.fsencode(path)))
+
+
+def seismic_index_load(path: str) -> int:
+    h = ctypes.c_void_p()
+    _check(load().seismic_index_load(os.fsencode(path), ctypes.byref(h)))
+    return h.value
+
+
+def seismic_index_info(handle) -> dict:
+    out = np.zeros(10, dtype=np.uint64)
+    _check(load().seismic_index_info(handle, _ptr(out)))
+    keys = ("dim", "n_docs", "nnz", "n_blocks", "n_postings", "n_summary", "lam", "beta",
+            "max_blocks_per_list", "on_device")
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
+def seismic_index_upload(handle, device: int = 0):
+    _check(load().seismic_index_upload(handle, device))
+
+
+def seismic_index_free(handle):
+    if handle:
+        load().seismic_index_free(handle)
+
+
+def seismic_workspace_create(handle, max_queries: int, max_k: int) -> int:
+    w = ctypes.c_void_p()
+    _check(load().seismic_workspace_create(handle, max_queries, max_k, ctypes.byref(w)))
+    return w.value
+
+
+def seismic_workspace_free(ws):
+    if ws:
+        load().seismic_workspace_free(ws)
+
+
+def seismic_search_batch(handle, ws, queries: Csr, k: int, query_cut: int, heap_factor: float,
+                         out_ids, out_scores, prefix=None, prefix_stride: int = 0, counters=None,
+                         stream=None, flags: int = 0):
+    p = SearchParams(k, query_cut, heap_factor, flags)
+    st = Stats(_ptr(prefix), prefix_stride, 0, _ptr(counters))
+    use_stats = prefix is not None or counters is not None
+    _check(load().seismic_search_batch(handle, ws, ctypes.byref(queries), ctypes.byref(p), _ptr(out_ids),
+                                       _ptr(out_scores), ctypes.byref(st) if use_stats else None,
+                                       _stream_handle(stream)))
+
+
+def exact_topk(handle, queries: Csr, k: int, out_ids, out_scores, stream=None):
+    _check(load().exact_topk(handle, ctypes.byref(queries), k, _ptr(out_ids), _ptr(out_scores),
+                             _stream_handle(stream)))

@@ -1,0 +1,289 @@
+// Device-side runtime of libseismic: index upload, workspaces and the
+// search / exact-search entry points of the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+#include "search_kernels.h"
+
+using namespace seismic;
+using seismic_dev::DevIdx;
+
+#define HIP_TRY(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) return fail(SEISMIC_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+struct DeviceIndex {
+    int device = -1;
+    DevIdx view{};
+    uint32_t sort_cap = 2;
+    size_t smem_limit = 0;
+    std::vector<void*> allocs;
+    // full inverted index for exact search (built on first use)
+    uint64_t* csc_off = nullptr;
+    uint32_t* csc_doc = nullptr;
+    uint16_t* csc_val = nullptr;
+    // staging for host-resident queries of exact search
+    uint64_t* xq_ptr = nullptr;
+    uint32_t* xq_words = nullptr;
+    size_t xq_rows_cap = 0, xq_words_cap = 0;
+};
+
+void device_index_free(DeviceIndex* d) {
+    if (!d) return;
+    int prev = 0;
+    bool switched = hipGetDevice(&prev) == hipSuccess && d->device >= 0 && hipSetDevice(d->device) == hipSuccess;
+    for (void* p : d->allocs) (void)hipFree(p);
+    (void)hipFree(d->csc_off);
+    (void)hipFree(d->csc_doc);
+    (void)hipFree(d->csc_val);
+    (void)hipFree(d->xq_ptr);
+    (void)hipFree(d->xq_words);
+    if (switched) (void)hipSetDevice(prev);
+    delete d;
+}
+
+namespace {
+
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev) {
+        ok_ = hipGetDevice(&prev_) == hipSuccess && hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (ok_) (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return ok_; }
+
+  private:
+    int prev_ = 0;
+    bool ok_ = false;
+};
+
+template <typename T>
+int upload_vec(DeviceIndex* d, const std::vector<T>& v, const T*& out) {
+    size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return fail(SEISMIC_ENOMEM, "upload: hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    d->allocs.push_back(p);
+    if (!v.empty()) {
+        e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(SEISMIC_EHIP, "upload: hipMemcpy: %s", hipGetErrorString(e));
+    }
+    out = (const T*)p;
+    return SEISMIC_OK;
+}
+
+int grow(void** p, size_t& cap, size_t need, size_t elem) {
+    if (need <= cap) return SEISMIC_OK;
+    size_t n = std::max(need, cap * 2);
+    (void)hipFree(*p);
+    *p = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc(p, std::max<size_t>(n * elem, 16));
+    if (e != hipSuccess) return fail(SEISMIC_ENOMEM, "staging: hipMalloc: %s", hipGetErrorString(e));
+    cap = n;
+    return SEISMIC_OK;
+}
+
+}  // namespace
+
+struct seismic_workspace {
+    const seismic_index* index = nullptr;
+    int device = -1;
+    uint32_t max_queries = 0, max_k = 0;
+    uint64_t* q_ptr = nullptr;  // staging for host-resident queries
+    uint32_t* q_words = nullptr;
+    size_t q_rows_cap = 0, q_words_cap = 0;
+};
+
+extern "C" {
+
+int seismic_index_upload(seismic_index* index, int device) {
+    if (!index) return fail(SEISMIC_EINVAL, "upload: null index");
+    std::lock_guard<std::mutex> lk(index->mu);
+    if (index->dev) return fail(SEISMIC_ESTATE, "upload: index already on device %d", index->dev->device);
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(SEISMIC_EINVAL, "upload: device %d of %d", device, ndev);
+    const HostIndex& h = index->h;
+    uint32_t mb = h.max_blocks_per_list();
+    uint32_t cap = 2;
+    while (cap < mb) cap <<= 1;
+    if (cap > seismic_dev::kMaxSortCap)
+        return fail(SEISMIC_EINVAL, "upload: a list has %u blocks; at most %u are supported", mb, seismic_dev::kMaxSortCap);
+    DeviceGuard g(device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "upload: cannot select device %d", device);
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    DeviceIndex* d = new DeviceIndex();
+    d->device = device;
+    d->sort_cap = cap;
+    d->smem_limit = prop.sharedMemPerBlock;
+    DevIdx& v = d->view;
+    int rc = 0;
+    if (!rc) rc = upload_vec(d, h.row_ptr, v.row_ptr);
+    if (!rc) rc = upload_vec(d, h.words, v.words);
+    if (!rc) rc = upload_vec(d, h.list_off, v.list_off);
+    if (!rc) rc = upload_vec(d, h.blk_post_off, v.blk_post_off);
+    if (!rc) rc = upload_vec(d, h.blk_sum_off, v.blk_sum_off);
+    if (!rc) rc = upload_vec(d, h.blk_m, v.blk_m);
+    if (!rc) rc = upload_vec(d, h.blk_delta, v.blk_delta);
+    if (!rc) rc = upload_vec(d, h.postings, v.postings);
+    if (!rc) rc = upload_vec(d, h.sum_term, v.sum_term);
+    if (!rc) rc = upload_vec(d, h.sum_code, v.sum_code);
+    if (rc) { device_index_free(d); return rc; }
+    v.dim = h.dim;
+    v.n_docs = (uint32_t)h.n_docs;
+    index->dev = d;
+    return SEISMIC_OK;
+}
+
+int seismic_workspace_create(const seismic_index* index, uint32_t max_queries, uint32_t max_k, seismic_workspace** out) {
+    if (!index || !out) return fail(SEISMIC_EINVAL, "workspace: null argument");
+    *out = nullptr;
+    if (!index->dev) return fail(SEISMIC_ESTATE, "workspace: index is not on a device");
+    if (max_k < 1 || max_k > SEISMIC_MAX_K) return fail(SEISMIC_EINVAL, "workspace: max_k must be in [1, %d]", SEISMIC_MAX_K);
+    size_t smem = seismic_dev::search_v1_smem_bytes(index->h.dim, index->dev->sort_cap, max_k);
+    if (smem > index->dev->smem_limit)
+        return fail(SEISMIC_EINVAL, "workspace: k = %u needs %zu bytes of LDS, the device allows %zu", max_k, smem,
+                    index->dev->smem_limit);
+    seismic_workspace* ws = new (std::nothrow) seismic_workspace();
+    if (!ws) return fail(SEISMIC_ENOMEM, "workspace: host allocation failed");
+    ws->index = index;
+    ws->device = index->dev->device;
+    ws->max_queries = max_queries;
+    ws->max_k = max_k;
+    *out = ws;
+    return SEISMIC_OK;
+}
+
+void seismic_workspace_free(seismic_workspace* ws) {
+    if (!ws) return;
+    DeviceGuard g(ws->device);
+    (void)hipFree(ws->q_ptr);
+    (void)hipFree(ws->q_words);
+    delete ws;
+}
+
+int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, const seismic_csr* queries,
+                         const seismic_search_params* params, uint32_t* out_ids, float* out_scores,
+                         const seismic_stats* stats, void* stream) {
+    if (!index || !ws || !queries || !params || !out_ids || !out_scores)
+        return fail(SEISMIC_EINVAL, "search: null argument");
+    if (!index->dev) return fail(SEISMIC_ESTATE, "search: index is not on a device");
+    if (ws->index != index) return fail(SEISMIC_EINVAL, "search: workspace belongs to another index");
+    if (params->k < 1 || params->k > ws->max_k) return fail(SEISMIC_EINVAL, "search: k = %u outside [1, %u]", params->k, ws->max_k);
+    if (!(params->heap_factor > 0.0f)) return fail(SEISMIC_EINVAL, "search: heap_factor must be > 0");
+    if (params->flags != 0) return fail(SEISMIC_EINVAL, "search: unknown flags");
+    if (queries->dim != index->h.dim) return fail(SEISMIC_EINVAL, "search: query dim %u != index dim %u", queries->dim, index->h.dim);
+    if (queries->n_rows > ws->max_queries)
+        return fail(SEISMIC_EINVAL, "search: %llu queries exceed the workspace (%u)", (unsigned long long)queries->n_rows, ws->max_queries);
+    if (stats && stats->prefix && stats->prefix_stride < 1) return fail(SEISMIC_EINVAL, "search: prefix_stride must be >= 1");
+    DeviceGuard g(ws->device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "search: cannot select device");
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t* q_ptr = queries->row_ptr;
+    const uint32_t* q_words = queries->words;
+    if (!queries->on_device) {
+        int rc = validate_csr_host(queries, SEISMIC_MAX_QUERY_NNZ, "search: queries");
+        if (rc) return rc;
+        rc = grow((void**)&ws->q_ptr, ws->q_rows_cap, queries->n_rows + 1, sizeof(uint64_t));
+        if (!rc) rc = grow((void**)&ws->q_words, ws->q_words_cap, std::max<uint64_t>(queries->nnz, 1), sizeof(uint32_t));
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(ws->q_ptr, queries->row_ptr, (queries->n_rows + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+        if (queries->nnz)
+            HIP_TRY(hipMemcpyAsync(ws->q_words, queries->words, queries->nnz * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        q_ptr = ws->q_ptr;
+        q_words = ws->q_words;
+    }
+    seismic_dev::SearchArgs a{};
+    a.ix = index->dev->view;
+    a.q_ptr = q_ptr;
+    a.q_words = q_words;
+    a.q_nnz = queries->nnz;
+    a.k = params->k;
+    a.cut = params->query_cut;
+    a.hf = params->heap_factor;
+    a.sort_cap = index->dev->sort_cap;
+    a.out_ids = out_ids;
+    a.out_scores = out_scores;
+    a.prefix = stats ? stats->prefix : nullptr;
+    a.prefix_stride = stats ? stats->prefix_stride : 0;
+    a.counters = stats ? stats->counters : nullptr;
+    size_t smem = seismic_dev::search_v1_smem_bytes(index->h.dim, index->dev->sort_cap, params->k);
+    HIP_TRY(seismic_dev::launch_search_v1(a, (uint32_t)queries->n_rows, smem, st));
+    return SEISMIC_OK;
+}
+
+int exact_topk(const seismic_index* index_c, const seismic_csr* queries, uint32_t k, uint32_t* out_ids,
+               float* out_scores, void* stream) {
+    seismic_index* index = const_cast<seismic_index*>(index_c);  // lazily extended device state
+    if (!index || !queries || !out_ids || !out_scores) return fail(SEISMIC_EINVAL, "exact_topk: null argument");
+    if (!index->dev) return fail(SEISMIC_ESTATE, "exact_topk: index is not on a device");
+    if (k < 1 || k > SEISMIC_MAX_K) return fail(SEISMIC_EINVAL, "exact_topk: k = %u outside [1, %d]", k, SEISMIC_MAX_K);
+    if (queries->dim != index->h.dim) return fail(SEISMIC_EINVAL, "exact_topk: query dim mismatch");
+    DeviceIndex* d = index->dev;
+    size_t smem = seismic_dev::exact_smem_bytes(k);
+    if (smem > d->smem_limit) return fail(SEISMIC_EINVAL, "exact_topk: k = %u needs %zu bytes of LDS (device allows %zu)", k, smem, d->smem_limit);
+    DeviceGuard g(d->device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "exact_topk: cannot select device");
+    std::lock_guard<std::mutex> lk(index->mu);
+    hipStream_t st = (hipStream_t)stream;
+    if (!d->csc_off) {
+        const HostIndex& h = index->h;
+        HostCSC csc;
+        try {
+            build_csc(h.row_ptr.data(), h.words.data(), h.n_docs, h.dim, 0, csc);
+        } catch (const std::bad_alloc&) {
+            return fail(SEISMIC_ENOMEM, "exact_topk: host allocation failed");
+        }
+        hipError_t e1 = hipMalloc((void**)&d->csc_off, csc.off.size() * 8);
+        hipError_t e2 = hipMalloc((void**)&d->csc_doc, std::max<size_t>(csc.doc.size() * 4, 16));
+        hipError_t e3 = hipMalloc((void**)&d->csc_val, std::max<size_t>(csc.val.size() * 2, 16));
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            (void)hipFree(d->csc_off); (void)hipFree(d->csc_doc); (void)hipFree(d->csc_val);
+            d->csc_off = nullptr; d->csc_doc = nullptr; d->csc_val = nullptr;
+            return fail(SEISMIC_ENOMEM, "exact_topk: device allocation of the inverted index failed");
+        }
+        HIP_TRY(hipMemcpy(d->csc_off, csc.off.data(), csc.off.size() * 8, hipMemcpyHostToDevice));
+        if (!csc.doc.empty()) {
+            HIP_TRY(hipMemcpy(d->csc_doc, csc.doc.data(), csc.doc.size() * 4, hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(d->csc_val, csc.val.data(), csc.val.size() * 2, hipMemcpyHostToDevice));
+        }
+    }
+    const uint64_t* q_ptr = queries->row_ptr;
+    const uint32_t* q_words = queries->words;
+    if (!queries->on_device) {
+        int rc = validate_csr_host(queries, SEISMIC_MAX_QUERY_NNZ, "exact_topk: queries");
+        if (!rc) rc = grow((void**)&d->xq_ptr, d->xq_rows_cap, queries->n_rows + 1, sizeof(uint64_t));
+        if (!rc) rc = grow((void**)&d->xq_words, d->xq_words_cap, std::max<uint64_t>(queries->nnz, 1), sizeof(uint32_t));
+        if (rc) return rc;
+        HIP_TRY(hipMemcpy(d->xq_ptr, queries->row_ptr, (queries->n_rows + 1) * 8, hipMemcpyHostToDevice));
+        if (queries->nnz) HIP_TRY(hipMemcpy(d->xq_words, queries->words, queries->nnz * 4, hipMemcpyHostToDevice));
+        q_ptr = d->xq_ptr;
+        q_words = d->xq_words;
+    }
+    seismic_dev::ExactArgs a{};
+    a.csc_off = d->csc_off;
+    a.csc_doc = d->csc_doc;
+    a.csc_val = d->csc_val;
+    a.dim = index->h.dim;
+    a.n_docs = (uint32_t)index->h.n_docs;
+    a.q_ptr = q_ptr;
+    a.q_words = q_words;
+    a.q_nnz = queries->nnz;
+    a.k = k;
+    a.out_ids = out_ids;
+    a.out_scores = out_scores;
+    HIP_TRY(seismic_dev::launch_exact(a, (uint32_t)queries->n_rows, smem, st));
+    return SEISMIC_OK;
+}
+
+}  // extern "C"

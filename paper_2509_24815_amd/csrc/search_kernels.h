@@ -1,0 +1,52 @@
+// Kernel entry points and their argument blocks (host and device view).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace seismic_dev {
+
+constexpr uint32_t kMaxQ = 1024;       // query nonzeros handled per query (SEISMIC_MAX_QUERY_NNZ)
+constexpr uint32_t kMaxSortCap = 8192; // largest number of blocks in one list
+
+struct SearchArgs {
+    DevIdx ix;
+    const uint64_t* q_ptr;
+    const uint32_t* q_words;
+    uint64_t q_nnz;  // length of q_words: row offsets are clamped to it
+    uint32_t k;
+    uint32_t cut;
+    float hf;
+    uint32_t sort_cap;  // power of two >= the largest list's block count
+    uint32_t* out_ids;
+    float* out_scores;
+    uint16_t* prefix;
+    uint32_t prefix_stride;
+    uint64_t* counters;
+};
+
+size_t search_v1_smem_bytes(uint32_t dim, uint32_t sort_cap, uint32_t k);
+hipError_t launch_search_v1(const SearchArgs& a, uint32_t nq, size_t smem, hipStream_t stream);
+
+// Exact search over a full inverted index (term -> doc-ascending postings).
+struct ExactArgs {
+    const uint64_t* csc_off;  // [dim+1]
+    const uint32_t* csc_doc;
+    const uint16_t* csc_val;
+    uint32_t dim;
+    uint32_t n_docs;
+    const uint64_t* q_ptr;
+    const uint32_t* q_words;
+    uint64_t q_nnz;
+    uint32_t k;
+    uint32_t* out_ids;
+    float* out_scores;
+};
+
+size_t exact_smem_bytes(uint32_t k);
+hipError_t launch_exact(const ExactArgs& a, uint32_t nq, size_t smem, hipStream_t stream);
+
+}  // namespace seismic_dev

@@ -1,0 +1,156 @@
+"""GPU parity: seismic_search_batch and exact_topk through the C ABI against
+the CPU oracle on the same seeded inputs and the same serialized index.
+
+Scores are exact on both sides (fp64 sums of exact products; values in
+[2^-6, 2^6]), so ids, scores, prefix lengths and counters must match bit for
+bit.  Near-tie prune decisions (|r*hf - min| <= 1e-5 * min) are counted by
+the oracle and reported."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2509_24815_amd import Index, SeismicError, binding
+from tests.gpu_util import as_u32, compare_with_oracle, to_device_csr
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    """100k documents, lambda 1000, beta 50, gamma 0.4; 1000 Poisson(43) queries."""
+    import torch
+    _log("[cfg1] generating 100k docs / 1000 queries, building index")
+    docs = synth.docs(100_000, seed=0)
+    qs = synth.queries(1000, seed=0)
+    ix = Index.build(docs, lam=1000, beta=50, gamma=0.4, seed=0)
+    ref_ix = oracle.Index(ix.serialize())
+    torch.cuda.set_device(0)
+    ix.upload(0)
+    return docs, qs, ix, ref_ix
+
+
+def _gpu_search(ix, qcsr, k, cut, hf, stride):
+    import torch
+    out = ix.search(qcsr, k, cut, hf, stats=True, prefix_stride=stride)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("cut,hf,k", [(10, 0.8, 10), (5, 0.7, 10), (20, 0.9, 10), (10, 0.8, 100),
+                                      (10, float("inf"), 10), (3, 1.5, 1)])
+def test_search_parity_config1(cfg1, cut, hf, k):
+    docs, qs, ix, ref_ix = cfg1
+    _log(f"[parity cfg1] cut={cut} hf={hf} k={k}")
+    ref = ref_ix.pruned_search(qs, k, cut, hf, c_cap=cut)
+    gpu = _gpu_search(ix, to_device_csr(qs), k, cut, hf, cut)
+    bad = compare_with_oracle(gpu, ref, k, cut)
+    near = int((ref["counters"][:, 6] > 0).sum())
+    _log(f"  mismatching queries: {len(bad)}; queries with near-tie prune tests: {near}")
+    assert not bad
+    assert (gpu[3].cpu().numpy()[:, 6] == 0).all()  # status: rows valid
+
+
+def test_host_and_device_queries_agree(cfg1):
+    docs, qs, ix, _ = cfg1
+    _log("[host vs device queries]")
+    sub = qs.subset(range(200))
+    a = ix.search(binding.host_csr(sub.row_ptr, sub.words, sub.dim), 10, 10, 0.8)
+    b = ix.search(to_device_csr(sub), 10, 10, 0.8)
+    assert np.array_equal(as_u32(a[0]), as_u32(b[0]))
+    assert np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
+
+
+def test_exact_topk_parity(cfg1):
+    docs, qs, ix, _ = cfg1
+    _log("[exact_topk cfg1] 1000 queries, k=10")
+    ids, sc = ix.exact(to_device_csr(qs), 10)
+    e_ids, e_sc = oracle.exact_topk(docs, qs, 10)
+    assert np.array_equal(as_u32(ids), e_ids)
+    assert np.array_equal(sc.cpu().numpy(), e_sc)
+
+
+def test_exact_topk_k100_subset(cfg1):
+    docs, qs, ix, _ = cfg1
+    _log("[exact_topk cfg1] 100 queries, k=100")
+    sub = qs.subset(range(100))
+    ids, sc = ix.exact(binding.host_csr(sub.row_ptr, sub.words, sub.dim), 100)
+    e_ids, e_sc = oracle.exact_topk(docs, sub, 100)
+    assert np.array_equal(as_u32(ids), e_ids)
+    assert np.array_equal(sc.cpu().numpy(), e_sc)
+
+
+def test_recall_against_exact(cfg1):
+    docs, qs, ix, _ = cfg1
+    ids, _ = ix.search(to_device_csr(qs), 10, 10, 0.8)
+    e_ids, _ = ix.exact(to_device_csr(qs), 10)
+    a, b = as_u32(ids), as_u32(e_ids)
+    rec = np.mean([len(set(x) & set(y)) / 10 for x, y in zip(a, b)])
+    _log(f"  Recall@10 (cut 10, hf 0.8) = {rec:.4f}")
+    assert rec > 0.8
+
+
+def test_edge_queries(cfg1):
+    """Empty rows, rows whose terms have no list, a single nonzero, and a
+    query longer than every cut."""
+    docs, qs, ix, ref_ix = cfg1
+    _log("[edge queries]")
+    rows = [{}, {30521: 1.0}, {0: 2.0}, {t: 1.0 + (t % 7) * 0.25 for t in range(0, 600, 2)}]
+    eq = synth.make_csr(rows)
+    for cut, hf, k in ((0, 0.8, 10), (2, float("inf"), 5), (10, 0.8, 300)):
+        ref = ref_ix.pruned_search(eq, k, cut, hf, c_cap=300)
+        gpu = _gpu_search(ix, to_device_csr(eq), k, cut, hf, 300)
+        assert not compare_with_oracle(gpu, ref, k, 300)
+    ids, sc = ix.search(to_device_csr(eq), 10, 10, 0.8)
+    assert (as_u32(ids)[0] == 0xFFFFFFFF).all() and np.isneginf(sc.cpu().numpy()[0]).all()
+
+
+def test_invalid_device_rows_are_flagged_not_read_out_of_bounds(cfg1):
+    """Device-resident rows are checked by the kernel: a term >= dim is
+    ignored, unsorted or repeated terms and bad values are flagged."""
+    import torch
+    docs, qs, ix, _ = cfg1
+    _log("[invalid device rows]")
+    words = np.array([5 | (0x3C00 << 16), 40000 | (0x3C00 << 16),        # term beyond dim
+                      9 | (0x3C00 << 16), 7 | (0x3C00 << 16),            # unsorted
+                      11 | (0x0000 << 16),                               # zero value
+                      12 | (0x3C00 << 16), 12 | (0x3C00 << 16)], dtype=np.uint32)  # repeated
+    rp = np.array([0, 2, 4, 5, 7], dtype=np.uint64)
+    c = binding.device_csr(torch.from_numpy(rp.astype(np.int64)).cuda(),
+                           torch.from_numpy(words.view(np.int32)).cuda(), docs.dim)
+    ids, sc, pref, cnt = ix.search(c, 10, 10, 0.8, stats=True, prefix_stride=10)
+    st = cnt.cpu().numpy()[:, 6]
+    assert st[0] & 1 and st[1] & 2 and st[2] & 8 and st[3] & 2
+    with pytest.raises(SeismicError):
+        ix.search(binding.host_csr(rp, words, docs.dim), 10, 10, 0.8)  # host rows are validated
+
+
+def test_search_argument_errors(cfg1):
+    docs, qs, ix, _ = cfg1
+    sub = to_device_csr(qs.subset(range(4)))
+    for k, cut, hf in ((0, 10, 0.8), (10, 10, 0.0), (10, 10, float("nan")), (10, 10, -1.0)):
+        with pytest.raises(SeismicError) as e:
+            ix.search(sub, k, cut, hf, ws=ix.workspace(16, 16))
+        assert e.value.code == binding.EINVAL
+    with pytest.raises(SeismicError):
+        ix.search(sub, 20, 10, 0.8, ws=ix.workspace(16, 16))  # k above the workspace's max_k
+    with pytest.raises(SeismicError):
+        ix.search(to_device_csr(qs.subset(range(20))), 10, 10, 0.8, ws=ix.workspace(16, 16))
+
+
+def test_no_pruning_full_lists_equals_exact():
+    """With lambda above every list length, query_cut = all and pruning
+    disabled (hf = +inf) the method is exact search."""
+    _log("[hf=inf, lambda=inf, cut=all == exact]")
+    docs = synth.docs(3000, seed=2)
+    qs = synth.queries(100, seed=2)
+    ix = Index.build(docs, lam=10_000, beta=40, gamma=0.4, seed=1)
+    ix.upload(0)
+    ids, sc = ix.search(to_device_csr(qs), 10, 0, float("inf"))
+    e_ids, e_sc = oracle.exact_topk(docs, qs, 10)
+    assert np.array_equal(as_u32(ids), e_ids)
+    assert np.array_equal(sc.cpu().numpy(), e_sc)
