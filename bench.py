@@ -1,0 +1,256 @@
+"""Benchmark of batched Seismic query processing on one MI355X.
+
+A step is one seismic_search_batch call over one batch of synthetic queries
+(all hot-path steps: query cut, summary scoring, block ordering, pruned block
+evaluation, top-k).  The workload defaults to the 8.8M-document index
+(lambda 6000, beta 400, gamma 0.4) with 7000-query batches of uniform [5, 200]
+nonzeros, query_cut 10, k 10.
+
+Prints one JSON line.  value = queries per second over the timed steps at
+the fastest swept heap_factor whose Recall@10 (against GPU exact top-k) is at
+least the target; the inputs are resident in HBM before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: docs, queries, query law, lambda, beta, gamma, cut, heap factors swept
+    "msmarco-8.8M": dict(n_docs=8_841_823, n_queries=7000, qlaw="uniform", lam=6000, beta=400, gamma=0.4,
+                         cut=10, hfs=(0.7, 0.8, 0.9, 1.0, 1.25, 1.5, 2.0)),
+    "1M": dict(n_docs=1_000_000, n_queries=10_000, qlaw="poisson", lam=3000, beta=150, gamma=0.4,
+               cut=10, hfs=(0.7, 0.8, 0.9, 1.0, 1.25, 1.5)),
+    "100k": dict(n_docs=100_000, n_queries=1000, qlaw="poisson", lam=1000, beta=50, gamma=0.4,
+                 cut=10, hfs=(0.7, 0.8, 0.9, 1.0, 1.25)),
+}
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def alg_bytes(counters: np.ndarray, q_nnz: np.ndarray, k: int) -> np.ndarray:
+    """Algorithmic HBM bytes per query of one search (layout of the library):
+    query row 8 + 4 n_q; per visited list 8 (list offsets); per block of a
+    visited list 16 (summary offset, m, delta) + 3 per summary entry (u16
+    term + u8 code); per evaluated block 8 (posting offsets) + per document
+    4 (posting) + 16 (row offsets) + 4 per nonzero; results 8 k."""
+    c = counters.astype(np.float64)
+    return (8 + 4 * q_nnz + 8 * c[:, 7] + 16 * c[:, 1] + 3 * c[:, 0] + 8 * c[:, 2] + 20 * c[:, 3]
+            + 4 * c[:, 4] + 8 * k)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="msmarco-8.8M", choices=sorted(WORKLOADS))
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--recall", type=float, default=0.95)
+    ap.add_argument("--hf", type=float, default=None, help="skip the sweep and use this heap_factor")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget (0 = skip)")
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--profile-copy", action="store_true", help="also run a plain copy for counter calibration")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2509_24815_amd import Index, binding
+
+    for lib in (synth._LIB_PATH, binding.LIB_PATH):
+        if not os.path.exists(lib):
+            import __graft_entry__
+            __graft_entry__.build()
+            break
+    binding.load()
+    W = WORKLOADS[args.workload]
+    k = args.k
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+
+    t0 = time.time()
+    log(f"[bench] workload {args.workload}: generating {W['n_docs']} docs (host cores: {os.cpu_count()})")
+    docs = synth.docs(W["n_docs"], seed=0)
+    qs = synth.queries(W["n_queries"], seed=0, law=W["qlaw"])
+    log(f"[bench] generated {docs.nnz} doc nonzeros, {qs.nnz} query nonzeros ({time.time() - t0:.1f} s)")
+    t1 = time.time()
+    ix = Index.build(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, verbose=True)
+    build_s = time.time() - t1
+    info = ix.info()
+    log(f"[bench] index built in {build_s:.1f} s: {info}")
+    ix.upload(0)
+    log("[bench] index resident in HBM")
+
+    q_rp = torch.from_numpy(qs.row_ptr.astype(np.int64)).to(dev)
+    q_w = torch.from_numpy(qs.words.view(np.int32)).to(dev)
+    qcsr = binding.device_csr(q_rp, q_w, qs.dim)
+    nq = qs.n_rows
+    q_nnz = np.diff(qs.row_ptr.astype(np.int64))
+    ws = binding.seismic_workspace_create(ix.handle, nq, max(k, 100))
+    out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    out_sc = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    cut = W["cut"]
+    prefix = torch.zeros((nq, cut), dtype=torch.int16, device=dev)
+    counters = torch.zeros((nq, 8), dtype=torch.int64, device=dev)
+
+    # ground truth
+    t2 = time.time()
+    ex_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    ex_sc = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    binding.exact_topk(ix.handle, qcsr, k, ex_ids, ex_sc, stream)
+    torch.cuda.synchronize()
+    exact_s = time.time() - t2
+    log(f"[bench] exact top-{k} of {nq} queries on the GPU: {exact_s:.2f} s")
+    ex = ex_ids.cpu().numpy().view(np.uint32)
+    ex_s = ex_sc.cpu().numpy()
+
+    def recall_of(ids_np, sc_np):
+        strict, tie = [], []
+        for a, b, bs, asc in zip(ids_np, ex, ex_s, sc_np):
+            valid = b != 0xFFFFFFFF
+            n = int(valid.sum())
+            if n == 0:
+                continue
+            strict.append(len(set(a[a != 0xFFFFFFFF]) & set(b[valid])) / n)
+            kth = bs[valid][-1]
+            tie.append(min(n, int((asc[a != 0xFFFFFFFF] >= kth).sum())) / n)
+        return float(np.mean(strict)), float(np.mean(tie))
+
+    def run(hf, with_stats):
+        binding.seismic_search_batch(ix.handle, ws, qcsr, k, cut, hf, out_ids, out_sc,
+                                     prefix if with_stats else None, cut if with_stats else 0,
+                                     counters if with_stats else None, stream)
+
+    # sweep heap_factor (Alg. 2 skip rule r * hf < heap.min: larger hf prunes less)
+    sweep = []
+    hfs = [args.hf] if args.hf else list(W["hfs"])
+    chosen = None
+    for hf in hfs:
+        run(hf, True)
+        torch.cuda.synchronize()
+        ts = time.time()
+        for _ in range(2):
+            run(hf, False)
+        torch.cuda.synchronize()
+        dt = (time.time() - ts) / 2
+        rs, rt = recall_of(out_ids.cpu().numpy().view(np.uint32), out_sc.cpu().numpy())
+        cnt = counters.cpu().numpy()
+        point = dict(hf=hf, recall=round(rs, 4), recall_tie_aware=round(rt, 4), qps=round(nq / dt, 1),
+                     docs_evaluated=float(cnt[:, 3].mean()), blocks_evaluated=float(cnt[:, 2].mean()))
+        sweep.append(point)
+        log(f"[bench] sweep {point}")
+        if chosen is None and rs >= args.recall:
+            chosen = hf
+        if chosen is not None and not args.hf:
+            break
+    if chosen is None:
+        chosen = max(sweep, key=lambda p: p["recall"])["hf"]
+        log(f"[bench] no swept heap_factor reached Recall@10 {args.recall}; using the best ({chosen})")
+    point = next(p for p in sweep if p["hf"] == chosen)
+
+    # algorithmic bytes of the chosen point
+    run(chosen, True)
+    torch.cuda.synchronize()
+    cnt = counters.cpu().numpy()
+    bytes_per_launch = float(alg_bytes(cnt, q_nnz, k).sum())
+
+    # timed steps
+    for _ in range(args.warmup):
+        run(chosen, False)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = time.time()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        run(chosen, False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - ts
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    qps = nq * args.steps / (gpu_ms / 1e3)
+    achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
+    log(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step, {qps:.0f} QPS, wall {wall:.2f} s, "
+        f"{achieved:.1f} GB/s algorithmic")
+
+    if args.profile_copy:
+        n = 1 << 28
+        a = torch.empty(n, dtype=torch.uint8, device=dev)
+        b = torch.empty(n, dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {n} bytes")
+
+    # CPU baseline: the oracle on a bounded sample of the same queries
+    cpu = None
+    if args.cpu_seconds > 0:
+        import oracle
+        oracle.build() if not os.path.exists(oracle._LIB_PATH) else None
+        log("[bench] CPU baseline: serializing the index for the oracle")
+        buf = ix.serialize()
+        ref = oracle.Index(buf)
+        threads = os.cpu_count() or 1
+        pilot = qs.subset(range(min(nq, 4 * threads)))
+        tp = time.time()
+        ref.pruned_search(pilot, k, cut, chosen, nthreads=threads, c_cap=cut)
+        per_q = (time.time() - tp) / pilot.n_rows
+        n_sample = int(max(threads, min(nq, args.cpu_seconds / max(per_q, 1e-9))))
+        sample = qs.subset(range(n_sample))
+        tc = time.time()
+        r = ref.pruned_search(sample, k, cut, chosen, nthreads=threads, c_cap=cut)
+        cpu_s = time.time() - tc
+        g_ids = out_ids.cpu().numpy().view(np.uint32)[:n_sample]
+        match = float((r["ids"] == g_ids).all(axis=1).mean())
+        cpu = {"value": round(n_sample / cpu_s, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {n_sample} of the {nq} queries, heap_factor {chosen}, {cpu_s:.1f} s",
+               "gpu_match_fraction": match}
+        log(f"[bench] CPU baseline {cpu}")
+        del ref, buf
+
+    out = {
+        "metric": "QPS at Recall@10>=0.95 (1 GPU, 8.8M docs); p50/p99 query latency",
+        "value": round(qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16xf16->f64 accumulate, f32 out",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {W['n_docs']} docs, {nq}-query batch ({W['qlaw']} nnz), "
+                               f"lambda {W['lam']}, beta {W['beta']}, gamma {W['gamma']}, query_cut {cut}, "
+                               f"k {k}, heap_factor {chosen}",
+                   "recall_at_10": point["recall"], "recall_target": args.recall,
+                   "index_build_s": round(build_s, 1), "exact_topk_s": round(exact_s, 2),
+                   "sweep": sweep},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "alg_bytes_per_launch": bytes_per_launch},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

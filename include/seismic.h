@@ -67,14 +67,15 @@ typedef struct {
    lambda entries (a list of n entries gets max(1, ceil(beta * n / lambda))
    blocks, empty clusters dropped); gamma = mass fraction kept by each
    block summary (gamma-MSS of the max vector, "summary" equation);
-   seed keys the centroid sampling; n_threads = host threads (0 = all). */
+   seed keys the centroid sampling; n_threads = host threads (0 = all);
+   verbose = 1 prints build phases and progress to stderr. */
 typedef struct {
     uint32_t lambda;
     uint32_t beta;
     double gamma;
     uint64_t seed;
     int32_t n_threads;
-    int32_t reserved;
+    int32_t verbose;
 } seismic_build_params;
 
 /* Search parameters (inputs of Algorithm 2): k results; query_cut = number

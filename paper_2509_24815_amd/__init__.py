@@ -20,8 +20,10 @@ class Index:
         self._ws = {}
 
     @classmethod
-    def build(cls, docs, lam: int, beta: int, gamma: float, seed: int = 0, n_threads: int = 0) -> "Index":
-        return cls(binding.seismic_build_index(docs.row_ptr, docs.words, docs.dim, lam, beta, gamma, seed, n_threads))
+    def build(cls, docs, lam: int, beta: int, gamma: float, seed: int = 0, n_threads: int = 0,
+              verbose: bool = False) -> "Index":
+        return cls(binding.seismic_build_index(docs.row_ptr, docs.words, docs.dim, lam, beta, gamma, seed,
+                                               n_threads, int(verbose)))
 
     @classmethod
     def load(cls, path: str) -> "Index":

@@ -1,6 +1,7 @@
 // Host side of libseismic: errors, threads, input validation, the index
 // builder of Section 4.4 and the serialized format.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -373,8 +374,13 @@ int build_host_index(const seismic_csr* docs, const seismic_build_params* p, Hos
         H.seed = p->seed;
         H.row_ptr.assign(docs->row_ptr, docs->row_ptr + docs->n_rows + 1);
         H.words.assign(docs->words, docs->words + docs->nnz);
+        auto t_start = std::chrono::steady_clock::now();
+        auto elapsed = [&]() {
+            return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        };
         HostCSC csc;
         build_csc(H.row_ptr.data(), H.words.data(), H.n_docs, dim, nthreads, csc);
+        if (p->verbose) std::fprintf(stderr, "build: inverted lists done (%.1f s, %d threads)\n", elapsed(), nthreads);
         std::vector<TermOut> outs(dim);
         // largest lists first for load balance
         std::vector<uint32_t> terms(dim);
@@ -386,11 +392,24 @@ int build_host_index(const seismic_csr* docs, const seismic_build_params* p, Hos
         });
         std::vector<std::unique_ptr<Scratch>> scratch(nthreads);
         for (auto& s : scratch) s.reset(new Scratch(dim));
+        uint64_t total_work = 0;
+        for (uint32_t t = 0; t < dim; ++t) total_work += std::min<uint64_t>(csc.off[t + 1] - csc.off[t], p->lambda);
+        std::atomic<uint64_t> done_work{0};
+        std::atomic<int> reported{0};
         parallel_for(dim, nthreads, 1, [&](int64_t i, int tid) {
             uint32_t t = terms[i];
             build_term(t, csc, H.row_ptr.data(), H.words.data(), *p, dim, *scratch[tid], outs[t]);
+            if (p->verbose && total_work) {
+                uint64_t w = std::min<uint64_t>(csc.off[t + 1] - csc.off[t], p->lambda);
+                uint64_t d = done_work.fetch_add(w) + w;
+                int pct = (int)(100 * d / total_work);
+                int prev = reported.load();
+                while (pct >= prev + 10 && !reported.compare_exchange_weak(prev, pct - pct % 10)) {}
+                if (pct >= prev + 10) std::fprintf(stderr, "build: lists %d%% (%.1f s)\n", pct - pct % 10, elapsed());
+            }
         });
         csc = HostCSC();
+        if (p->verbose) std::fprintf(stderr, "build: blocks and summaries done (%.1f s)\n", elapsed());
         // concatenate in term order
         uint64_t nb = 0, np = 0, ns = 0;
         for (auto& o : outs) { nb += o.m.size(); np += o.postings.size(); ns += o.sum_term.size(); }
