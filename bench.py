@@ -23,14 +23,18 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# heap_factor sweep, most pruning first (Algorithm 2 skip rule r * hf < heap.min):
+# the first point reaching the recall target is the fastest one that does.
+HF_SWEEP = (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.25, 1.5, 2.0)
+
 WORKLOADS = {
     # name: docs, queries, query law, lambda, beta, gamma, cut, heap factors swept
     "msmarco-8.8M": dict(n_docs=8_841_823, n_queries=7000, qlaw="uniform", lam=6000, beta=400, gamma=0.4,
-                         cut=10, hfs=(0.7, 0.8, 0.9, 1.0, 1.25, 1.5, 2.0)),
+                         cut=10, hfs=HF_SWEEP),
     "1M": dict(n_docs=1_000_000, n_queries=10_000, qlaw="poisson", lam=3000, beta=150, gamma=0.4,
-               cut=10, hfs=(0.7, 0.8, 0.9, 1.0, 1.25, 1.5)),
+               cut=10, hfs=HF_SWEEP),
     "100k": dict(n_docs=100_000, n_queries=1000, qlaw="poisson", lam=1000, beta=50, gamma=0.4,
-                 cut=10, hfs=(0.7, 0.8, 0.9, 1.0, 1.25)),
+                 cut=10, hfs=HF_SWEEP),
 }
 
 PEAK_HBM_GBS = 8000.0
@@ -104,6 +108,7 @@ def main():
     nq = qs.n_rows
     q_nnz = np.diff(qs.row_ptr.astype(np.int64))
     ws = binding.seismic_workspace_create(ix.handle, nq, max(k, 100))
+    binding.seismic_workspace_set_config(ws, 256, 0, 8)
     out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     out_sc = torch.empty((nq, k), dtype=torch.float32, device=dev)
     cut = W["cut"]

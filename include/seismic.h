@@ -149,6 +149,21 @@ int seismic_workspace_create(const seismic_index* index, uint32_t max_queries, u
                              seismic_workspace** out);
 void seismic_workspace_free(seismic_workspace* ws);
 
+/* Launch shape of the persistent search kernel held by a workspace:
+   threads per workgroup (256 or 512), resident workgroups per CU
+   (0 = as many as fit), and the speculation window (1..32 consecutive
+   blocks of a list gathered before their prune decisions are replayed in
+   order; results never depend on it).  EINVAL for unsupported shapes. */
+typedef struct {
+    uint32_t threads;
+    uint32_t blocks_per_cu;
+    uint32_t window;
+    uint32_t reserved;
+} seismic_launch_config;
+
+int seismic_workspace_set_config(seismic_workspace* ws, const seismic_launch_config* cfg);
+int seismic_workspace_get_config(const seismic_workspace* ws, seismic_launch_config* cfg);
+
 /*
  * Algorithm 2 (kappa = 0) for a batch of queries, asynchronously on stream.
  * out_ids [n_queries * k] u32 and out_scores [n_queries * k] f32 are device

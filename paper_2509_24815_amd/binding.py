@@ -45,6 +45,11 @@ class SearchParams(ctypes.Structure):
                 ("flags", ctypes.c_uint32)]
 
 
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32), ("window", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("prefix", ctypes.c_void_p), ("prefix_stride", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("counters", ctypes.c_void_p)]
@@ -73,6 +78,8 @@ def load():
         "seismic_index_free": ([vp], None),
         "seismic_workspace_create": ([vp, u32, u32, P(vp)], i32),
         "seismic_workspace_free": ([vp], None),
+        "seismic_workspace_set_config": ([vp, P(LaunchConfig)], i32),
+        "seismic_workspace_get_config": ([vp, P(LaunchConfig)], i32),
         "seismic_search_batch": ([vp, vp, P(Csr), P(SearchParams), vp, vp, P(Stats), vp], i32),
         "exact_topk": ([vp, P(Csr), u32, vp, vp, vp], i32),
     }
@@ -175,6 +182,17 @@ def seismic_workspace_create(handle, max_queries: int, max_k: int) -> int:
 def seismic_workspace_free(ws):
     if ws:
         load().seismic_workspace_free(ws)
+
+
+def seismic_workspace_set_config(ws, threads: int = 256, blocks_per_cu: int = 0, window: int = 4):
+    c = LaunchConfig(threads, blocks_per_cu, window, 0)
+    _check(load().seismic_workspace_set_config(ws, ctypes.byref(c)))
+
+
+def seismic_workspace_get_config(ws) -> dict:
+    c = LaunchConfig()
+    _check(load().seismic_workspace_get_config(ws, ctypes.byref(c)))
+    return {"threads": c.threads, "blocks_per_cu": c.blocks_per_cu, "window": c.window}
 
 
 def seismic_search_batch(handle, ws, queries: Csr, k: int, query_cut: int, heap_factor: float,

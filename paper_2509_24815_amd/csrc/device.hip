@@ -65,13 +65,19 @@ class DeviceGuard {
     bool ok_ = false;
 };
 
+// pad: extra zeroed elements after the data (vector loads may overrun the
+// last group of a section by up to pad elements)
 template <typename T>
-int upload_vec(DeviceIndex* d, const std::vector<T>& v, const T*& out) {
-    size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+int upload_vec(DeviceIndex* d, const std::vector<T>& v, const T*& out, size_t pad = 0) {
+    size_t bytes = std::max<size_t>((v.size() + pad) * sizeof(T), 16);
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) return fail(SEISMIC_ENOMEM, "upload: hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
     d->allocs.push_back(p);
+    if (pad) {
+        e = hipMemset((uint8_t*)p + v.size() * sizeof(T), 0, bytes - v.size() * sizeof(T));
+        if (e != hipSuccess) return fail(SEISMIC_EHIP, "upload: hipMemset: %s", hipGetErrorString(e));
+    }
     if (!v.empty()) {
         e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
         if (e != hipSuccess) return fail(SEISMIC_EHIP, "upload: hipMemcpy: %s", hipGetErrorString(e));
@@ -98,10 +104,27 @@ struct seismic_workspace {
     const seismic_index* index = nullptr;
     int device = -1;
     uint32_t max_queries = 0, max_k = 0;
+    int n_cu = 0;
+    seismic_launch_config cfg{256, 0, 8, 0};
+    uint32_t* queue = nullptr;  // device counter of the persistent search kernel
     uint64_t* q_ptr = nullptr;  // staging for host-resident queries
     uint32_t* q_words = nullptr;
     size_t q_rows_cap = 0, q_words_cap = 0;
 };
+
+namespace {
+
+int check_config(const seismic_workspace* ws, const seismic_launch_config* c) {
+    if (c->threads != 256 && c->threads != 512) return fail(SEISMIC_EINVAL, "config: threads must be 256 or 512");
+    if (c->window < 1 || c->window > seismic_dev::kMaxW)
+        return fail(SEISMIC_EINVAL, "config: window must be in [1, %u]", seismic_dev::kMaxW);
+    size_t smem = seismic_dev::search_smem_bytes(c->threads, ws->index->h.dim, ws->index->dev->sort_cap, ws->max_k);
+    if (smem > ws->index->dev->smem_limit)
+        return fail(SEISMIC_EINVAL, "config: %zu bytes of LDS needed, the device allows %zu", smem, ws->index->dev->smem_limit);
+    return SEISMIC_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -129,15 +152,15 @@ int seismic_index_upload(seismic_index* index, int device) {
     DevIdx& v = d->view;
     int rc = 0;
     if (!rc) rc = upload_vec(d, h.row_ptr, v.row_ptr);
-    if (!rc) rc = upload_vec(d, h.words, v.words);
+    if (!rc) rc = upload_vec(d, h.words, v.words, 8);
     if (!rc) rc = upload_vec(d, h.list_off, v.list_off);
     if (!rc) rc = upload_vec(d, h.blk_post_off, v.blk_post_off);
     if (!rc) rc = upload_vec(d, h.blk_sum_off, v.blk_sum_off);
     if (!rc) rc = upload_vec(d, h.blk_m, v.blk_m);
     if (!rc) rc = upload_vec(d, h.blk_delta, v.blk_delta);
     if (!rc) rc = upload_vec(d, h.postings, v.postings);
-    if (!rc) rc = upload_vec(d, h.sum_term, v.sum_term);
-    if (!rc) rc = upload_vec(d, h.sum_code, v.sum_code);
+    if (!rc) rc = upload_vec(d, h.sum_term, v.sum_term, 16);
+    if (!rc) rc = upload_vec(d, h.sum_code, v.sum_code, 16);
     if (rc) { device_index_free(d); return rc; }
     v.dim = h.dim;
     v.n_docs = (uint32_t)h.n_docs;
@@ -150,16 +173,25 @@ int seismic_workspace_create(const seismic_index* index, uint32_t max_queries, u
     *out = nullptr;
     if (!index->dev) return fail(SEISMIC_ESTATE, "workspace: index is not on a device");
     if (max_k < 1 || max_k > SEISMIC_MAX_K) return fail(SEISMIC_EINVAL, "workspace: max_k must be in [1, %d]", SEISMIC_MAX_K);
-    size_t smem = seismic_dev::search_v1_smem_bytes(index->h.dim, index->dev->sort_cap, max_k);
-    if (smem > index->dev->smem_limit)
-        return fail(SEISMIC_EINVAL, "workspace: k = %u needs %zu bytes of LDS, the device allows %zu", max_k, smem,
-                    index->dev->smem_limit);
     seismic_workspace* ws = new (std::nothrow) seismic_workspace();
     if (!ws) return fail(SEISMIC_ENOMEM, "workspace: host allocation failed");
     ws->index = index;
     ws->device = index->dev->device;
     ws->max_queries = max_queries;
     ws->max_k = max_k;
+    int rc = check_config(ws, &ws->cfg);
+    if (rc) { delete ws; return rc; }
+    DeviceGuard g(ws->device);
+    hipDeviceProp_t prop;
+    if (!g.ok() || hipGetDeviceProperties(&prop, ws->device) != hipSuccess) {
+        delete ws;
+        return fail(SEISMIC_EHIP, "workspace: cannot query device %d", index->dev->device);
+    }
+    ws->n_cu = prop.multiProcessorCount;
+    if (hipMalloc((void**)&ws->queue, 256) != hipSuccess) {
+        delete ws;
+        return fail(SEISMIC_ENOMEM, "workspace: device allocation failed");
+    }
     *out = ws;
     return SEISMIC_OK;
 }
@@ -167,9 +199,24 @@ int seismic_workspace_create(const seismic_index* index, uint32_t max_queries, u
 void seismic_workspace_free(seismic_workspace* ws) {
     if (!ws) return;
     DeviceGuard g(ws->device);
+    (void)hipFree(ws->queue);
     (void)hipFree(ws->q_ptr);
     (void)hipFree(ws->q_words);
     delete ws;
+}
+
+int seismic_workspace_set_config(seismic_workspace* ws, const seismic_launch_config* cfg) {
+    if (!ws || !cfg) return fail(SEISMIC_EINVAL, "config: null argument");
+    int rc = check_config(ws, cfg);
+    if (rc) return rc;
+    ws->cfg = *cfg;
+    return SEISMIC_OK;
+}
+
+int seismic_workspace_get_config(const seismic_workspace* ws, seismic_launch_config* cfg) {
+    if (!ws || !cfg) return fail(SEISMIC_EINVAL, "config: null argument");
+    *cfg = ws->cfg;
+    return SEISMIC_OK;
 }
 
 int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, const seismic_csr* queries,
@@ -212,13 +259,21 @@ int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, cons
     a.cut = params->query_cut;
     a.hf = params->heap_factor;
     a.sort_cap = index->dev->sort_cap;
+    a.nq = (uint32_t)queries->n_rows;
+    a.window = ws->cfg.window;
+    a.queue = ws->queue;
     a.out_ids = out_ids;
     a.out_scores = out_scores;
     a.prefix = stats ? stats->prefix : nullptr;
     a.prefix_stride = stats ? stats->prefix_stride : 0;
     a.counters = stats ? stats->counters : nullptr;
-    size_t smem = seismic_dev::search_v1_smem_bytes(index->h.dim, index->dev->sort_cap, params->k);
-    HIP_TRY(seismic_dev::launch_search_v1(a, (uint32_t)queries->n_rows, smem, st));
+    const uint32_t nt = ws->cfg.threads;
+    size_t smem = seismic_dev::search_smem_bytes(nt, index->h.dim, index->dev->sort_cap, params->k);
+    int per_cu = seismic_dev::search_blocks_per_cu(nt, smem);
+    if (per_cu < 1) return fail(SEISMIC_EHIP, "search: kernel does not fit on a CU (%zu bytes of LDS)", smem);
+    if (ws->cfg.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)ws->cfg.blocks_per_cu);
+    uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ws->n_cu, queries->n_rows);
+    HIP_TRY(seismic_dev::launch_search(a, nt, grid, smem, st));
     return SEISMIC_OK;
 }
 

@@ -6,7 +6,6 @@
 
 namespace seismic_dev {
 
-constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
 
 // The index as the kernels see it (all device pointers).
@@ -19,8 +18,8 @@ struct DevIdx {
     const float* blk_m;
     const float* blk_delta;
     const uint32_t* postings;
-    const uint16_t* sum_term;
-    const uint8_t* sum_code;
+    const uint16_t* sum_term;  // padded to a multiple of 8 entries (+8)
+    const uint8_t* sum_code;   // padded likewise
     uint32_t dim;
     uint32_t n_docs;
 };
@@ -36,6 +35,12 @@ __device__ __forceinline__ bool half_ok(uint32_t h) {
 // Result order: larger score first, then smaller id.
 __device__ __forceinline__ bool better(float s1, uint32_t d1, float s2, uint32_t d2) {
     return s1 > s2 || (s1 == s2 && d1 < d2);
+}
+
+__device__ __forceinline__ uint8_t* carve(uint8_t*& p, size_t bytes) {
+    uint8_t* out = p;
+    p += (bytes + 15) & ~size_t(15);
+    return out;
 }
 
 // Query held in LDS as a membership bitmap over terms plus per-word prefix
@@ -69,53 +74,74 @@ __device__ __forceinline__ T group_sum(T x) {
     return x;
 }
 
-// Exclusive prefix popcounts of bits[0..nw) into pref, by the whole block.
-// nw <= 1024.  Ends with a barrier.
-__device__ inline void build_prefix(const uint64_t* bits, uint16_t* pref, uint32_t nw, uint32_t* scratch) {
-    const int tid = threadIdx.x;
-    // each thread owns up to 4 consecutive words
-    uint32_t base = (uint32_t)tid * 4u, local = 0;
-    for (uint32_t i = 0; i < 4; ++i)
-        if (base + i < nw) local += (uint32_t)__popcll(bits[base + i]);
-    scratch[tid] = local;
-    __syncthreads();
-    if (tid < kWave) {  // wave 0 scans the 256 partial sums, 4 per lane
-        uint32_t s[4], run = 0;
-        for (int i = 0; i < 4; ++i) { s[i] = scratch[tid * 4 + i]; run += s[i]; }
-        uint32_t incl = run;
+// Block-wide exclusive scan of one value per thread.  scratch needs
+// NT/64 + 1 words.  Returns the exclusive prefix; *total gets the sum.
+// Contains two barriers; every thread must call it.
+template <int NT>
+__device__ __forceinline__ uint32_t block_exscan(uint32_t v, uint32_t* scratch, uint32_t* total) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    uint32_t incl = v;
 #pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            uint32_t y = __shfl_up(incl, o, kWave);
-            if (tid >= o) incl += y;
-        }
-        uint32_t ex = incl - run;
-        for (int i = 0; i < 4; ++i) { uint32_t v = s[i]; scratch[tid * 4 + i] = ex; ex += v; }
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) scratch[wave] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / kWave; ++w) {
+        uint32_t c = scratch[w];
+        base += (w < wave) ? c : 0u;
+        tot += c;
     }
     __syncthreads();
-    uint32_t ex = scratch[tid];
-    for (uint32_t i = 0; i < 4; ++i)
+    *total = tot;
+    return base + incl - v;
+}
+
+// Exclusive prefix popcounts of bits[0..nw) into pref (nw <= 16 * NT).
+template <int NT>
+__device__ inline void build_prefix(const uint64_t* bits, uint16_t* pref, uint32_t nw, uint32_t* scratch) {
+    const uint32_t per = (nw + NT - 1) / NT;
+    const uint32_t base = (uint32_t)threadIdx.x * per;
+    uint32_t local = 0;
+    for (uint32_t i = 0; i < per; ++i)
+        if (base + i < nw) local += (uint32_t)__popcll(bits[base + i]);
+    uint32_t tot;
+    uint32_t ex = block_exscan<NT>(local, scratch, &tot);
+    for (uint32_t i = 0; i < per; ++i)
         if (base + i < nw) { pref[base + i] = (uint16_t)ex; ex += (uint32_t)__popcll(bits[base + i]); }
     __syncthreads();
 }
 
-// Sorted top-k set in LDS: hs/hid hold hn entries in result order.  merge()
-// folds up to kBlock candidates (distinct ids, not yet filtered) into it and
-// keeps the k best distinct ids.  Called by the whole block; all threads must
-// pass the same (nc, k, hn).  Double-buffered: the caller swaps via `cur`.
+// Sorted top-k set in LDS, double-buffered: (s0, i0) and (s1, i1); `which`
+// selects the live copy.  hn entries are live, in result order.  merge()
+// folds up to NT candidates into it, keeping the k best distinct ids.
+// Every thread of the block calls merge with the same arguments.
+template <int NT>
 struct TopK {
-    float* hs[2];
-    uint32_t* hid[2];
-    float* cs;       // [kBlock] candidate scores
-    uint32_t* cid;   // [kBlock] candidate ids
-    uint32_t* flag;  // [kBlock + 32]
-    int cur;
+    float* s0;
+    float* s1;
+    uint32_t* i0;
+    uint32_t* i1;
+    float* cs;       // [2 * NT]: candidates, then survivors
+    uint32_t* cid;   // [2 * NT]
+    uint32_t* scratch;  // [NT / 64 + 1]
+    uint32_t which;
     uint32_t hn;
     uint32_t k;
 
-    __device__ __forceinline__ uint32_t lower_pos(float s, uint32_t d) const {
-        // number of heap entries better than (s, d)
-        const float* H = hs[cur];
-        const uint32_t* I = hid[cur];
+    __device__ __forceinline__ const float* hs() const { return which ? s1 : s0; }
+    __device__ __forceinline__ const uint32_t* hid() const { return which ? i1 : i0; }
+    __device__ __forceinline__ bool full() const { return hn == k; }
+    __device__ __forceinline__ float min_score() const { return hs()[k - 1]; }
+    __device__ __forceinline__ uint32_t min_id() const { return hid()[k - 1]; }
+
+    // number of live entries better than (s, d)
+    __device__ __forceinline__ uint32_t rank_in_heap(float s, uint32_t d) const {
+        const float* H = hs();
+        const uint32_t* I = hid();
         uint32_t lo = 0, hi = hn;
         while (lo < hi) {
             uint32_t mid = (lo + hi) >> 1;
@@ -124,8 +150,13 @@ struct TopK {
         return lo;
     }
 
-    // Candidates are in cs/cid[0..nc); the caller put them there and issued a
-    // barrier.  Candidates with a score <= 0 are ignored (not results).
+    // Would (s, d) enter the set right now (ignoring duplicates)?
+    __device__ __forceinline__ bool admits(float s, uint32_t d) const {
+        return s > 0.0f && (hn < k || better(s, d, min_score(), min_id()));
+    }
+
+    // Candidates in cs/cid[0..nc), written before a barrier.  Scores <= 0
+    // are not results and are ignored; ids already present are skipped.
     __device__ void merge(uint32_t nc) {
         const int tid = threadIdx.x;
         bool ok = false;
@@ -134,33 +165,22 @@ struct TopK {
         if ((uint32_t)tid < nc) {
             s = cs[tid];
             d = cid[tid];
-            uint32_t pos = lower_pos(s, d);
-            bool dup = pos < hn && hs[cur][pos] == s && hid[cur][pos] == d;
-            ok = s > 0.0f && !dup && (hn < k || better(s, d, hs[cur][hn - 1], hid[cur][hn - 1]));
+            const uint32_t pos = rank_in_heap(s, d);
+            const bool dup = pos < hn && hs()[pos] == s && hid()[pos] == d;
+            ok = !dup && admits(s, d);
         }
-        // compact survivors with a block-wide exclusive scan of ok
-        const int lane = tid & (kWave - 1), wave = tid / kWave;
-        uint64_t m = __ballot(ok);
-        uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) flag[kBlock + wave] = (uint32_t)__popcll(m);
-        __syncthreads();
-        uint32_t wbase = 0, ns = 0;
-        for (int w = 0; w < kBlock / kWave; ++w) {
-            uint32_t c = flag[kBlock + w];
-            if (w < wave) wbase += c;
-            ns += c;
-        }
-        // survivors go to the top of the candidate arrays' second half
-        float* ss = cs + kBlock;
-        uint32_t* sd = cid + kBlock;
-        if (ok) { ss[wbase + before] = s; sd[wbase + before] = d; }
+        uint32_t ns;
+        const uint32_t at = block_exscan<NT>(ok ? 1u : 0u, scratch, &ns);
+        float* ss = cs + NT;
+        uint32_t* sd = cid + NT;
+        if (ok) { ss[at] = s; sd[at] = d; }
         __syncthreads();
         if (ns == 0) return;
-        const float* H = hs[cur];
-        const uint32_t* I = hid[cur];
-        float* NH = hs[cur ^ 1];
-        uint32_t* NI = hid[cur ^ 1];
-        for (uint32_t e = (uint32_t)tid; e < hn + ns; e += kBlock) {
+        const float* H = hs();
+        const uint32_t* I = hid();
+        float* NH = which ? s0 : s1;
+        uint32_t* NI = which ? i0 : i1;
+        for (uint32_t e = (uint32_t)tid; e < hn + ns; e += NT) {
             float es;
             uint32_t ed, rank;
             if (e < hn) {
@@ -168,7 +188,7 @@ struct TopK {
                 rank = e;
             } else {
                 es = ss[e - hn]; ed = sd[e - hn];
-                rank = lower_pos(es, ed);
+                rank = rank_in_heap(es, ed);
             }
             for (uint32_t j = 0; j < ns; ++j)
                 if (better(ss[j], sd[j], es, ed)) ++rank;
@@ -176,7 +196,7 @@ struct TopK {
         }
         __syncthreads();
         hn = min(k, hn + ns);
-        cur ^= 1;
+        which ^= 1u;
     }
 };
 

@@ -15,6 +15,7 @@
 
 namespace seismic_dev {
 
+constexpr int kBlock = 256;
 constexpr uint32_t kRange = 2048;
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 
@@ -69,15 +70,15 @@ __global__ __launch_bounds__(kBlock) void k_exact(ExactArgs a) {
     float* qv = (float*)xbump(p, 4ull * kMaxQ);
     uint32_t* scratch = (uint32_t*)xbump(p, 4ull * (kBlock + 1));
     uint32_t* misc = (uint32_t*)xbump(p, 4ull * 8);
-    TopK top;
-    top.hs[0] = (float*)xbump(p, 4ull * a.k);
-    top.hs[1] = (float*)xbump(p, 4ull * a.k);
-    top.hid[0] = (uint32_t*)xbump(p, 4ull * a.k);
-    top.hid[1] = (uint32_t*)xbump(p, 4ull * a.k);
+    TopK<kBlock> top;
+    top.s0 = (float*)xbump(p, 4ull * a.k);
+    top.s1 = (float*)xbump(p, 4ull * a.k);
+    top.i0 = (uint32_t*)xbump(p, 4ull * a.k);
+    top.i1 = (uint32_t*)xbump(p, 4ull * a.k);
     top.cs = (float*)xbump(p, 4ull * 2 * kBlock);
     top.cid = (uint32_t*)xbump(p, 4ull * 2 * kBlock);
-    top.flag = (uint32_t*)xbump(p, 4ull * (kBlock + 32));
-    top.cur = 0;
+    top.scratch = scratch;
+    top.which = 0;
     top.hn = 0;
     top.k = a.k;
 
@@ -153,8 +154,8 @@ __global__ __launch_bounds__(kBlock) void k_exact(ExactArgs a) {
         }
         // offer the range's documents, at most one per thread per round
         for (;;) {
-            const float hmin_s = top.hn == top.k ? top.hs[top.cur][top.k - 1] : 0.0f;
-            const uint32_t hmin_d = top.hn == top.k ? top.hid[top.cur][top.k - 1] : 0u;
+            const float hmin_s = top.full() ? top.min_score() : 0.0f;
+            const uint32_t hmin_d = top.full() ? top.min_id() : 0u;
             float bs = 0.0f;
             uint32_t bi = kInf;
             for (uint32_t i = tid; i < e - s; i += kBlock) {
@@ -173,14 +174,15 @@ __global__ __launch_bounds__(kBlock) void k_exact(ExactArgs a) {
             uint32_t tot = 0;
             for (int w = 0; w < kBlock / kWave; ++w) tot += scratch[w];
             if (tot == 0) break;
+            __syncthreads();  // everyone has read scratch before merge reuses it
             top.merge(kBlock);
         }
         __syncthreads();
     }
     for (uint32_t i = tid; i < a.k; i += kBlock) {
         const bool have = i < top.hn;
-        a.out_ids[(size_t)qi * a.k + i] = have ? top.hid[top.cur][i] : 0xFFFFFFFFu;
-        a.out_scores[(size_t)qi * a.k + i] = have ? top.hs[top.cur][i] : -INFINITY;
+        a.out_ids[(size_t)qi * a.k + i] = have ? top.hid()[i] : 0xFFFFFFFFu;
+        a.out_scores[(size_t)qi * a.k + i] = have ? top.hs()[i] : -INFINITY;
     }
 }
 
@@ -188,7 +190,7 @@ size_t exact_smem_bytes(uint32_t k) {
     auto r16 = [](size_t x) { return (x + 15) & ~size_t(15); };
     size_t s = r16(8ull * kRange) + 2 * r16(8ull * kMaxQ) + 2 * r16(4ull * kMaxQ) + r16(4ull * (kMaxQ + 1));
     s += 2 * r16(4ull * kMaxQ) + r16(4ull * (kBlock + 1)) + r16(32);
-    s += 4 * r16(4ull * k) + 2 * r16(4ull * 2 * kBlock) + r16(4ull * (kBlock + 32));
+    s += 4 * r16(4ull * k) + 2 * r16(4ull * 2 * kBlock);
     return s;
 }
 

@@ -1,260 +1,615 @@
 // Algorithm 2 ("Query processing with Seismic", Section 4.5) with the
-// kappa-NN refinement disabled: one workgroup answers one query.
+// kappa-NN refinement disabled.  One workgroup of NT threads answers one
+// query at a time; a persistent grid pulls query indices from a device
+// counter.
 //
-//   1. query ingest: membership bitmap + prefix counts + values in LDS; the
-//      cut keeps the query_cut largest entries (value desc, term asc);
+//   1. ingest: the query becomes a dense u8 slot table over all terms in LDS
+//      (slot 0 = absent) plus an fp64 value per slot, value[0] = 0, so every
+//      lookup is two LDS reads and no branch; queries with more than 255
+//      distinct terms use a membership bitmap with prefix counts instead.
+//      The cut keeps the query_cut largest entries (value desc, term asc);
 //   2. per cut list, in cut order:
-//      a. summary scores r_j = <q, S_j> of every block (one wave per block,
-//         lanes stride the block's (term, code) entries), in fp64 as
-//         m * sum(q) + delta * sum(q * code), exact for values in
-//         [2^-6, 2^6] because m and delta sit on the 2^-14 grid;
-//      b. LDS bitonic sort of (r desc, block asc);
-//      c. blocks in that order until the first one with a full heap and
-//         r * heap_factor < heap.min: every document of the block is scored
-//         exactly (16 lanes per document, fp64 sum of exact fp32 products)
-//         and folded into the LDS top-k.
+//      a. summary scores r_j = <q, S_j> of every block: the list's summary
+//         entries are one contiguous run, streamed by the whole workgroup in
+//         16-byte groups of 8 entries; per block, sum(q) and sum(q * code)
+//         are gathered in LDS fp64 and r_j = m_j * sum(q) + delta_j *
+//         sum(q * code) (exact for values in [2^-6, 2^6]: m and delta sit on
+//         the 2^-14 grid, so every term is a multiple of 2^-30 below 2^23);
+//      b. blocks that can never be evaluated in this list (full heap and
+//         r * heap_factor < heap.min, which only grows) are dropped, the rest
+//         sorted in LDS by (r desc, block asc) with a bitonic network;
+//      c. traversal in that order: up to W consecutive blocks (at most NT
+//         documents) are gathered at once - a thread per document fetches
+//         its posting and row offsets, then groups of 8 lanes stream whole
+//         rows as 16-byte loads and accumulate exact products in fp64 - and
+//         the blocks are then replayed one by one: a block is evaluated
+//         unless the heap is full and r * heap_factor < heap.min, which ends
+//         the list; an evaluated block's documents are folded into the LDS
+//         top-k.  Replaying in order keeps every decision identical to the
+//         sequential algorithm; blocks gathered past a stop are wasted work.
 #include "device_common.h"
 #include "search_kernels.h"
 
 namespace seismic_dev {
 
-struct SearchSmem {
-    QTable q;
-    uint16_t* q_term;  // [kMaxQ] 0xFFFF = dropped entry
-    uint16_t* q_half;  // [kMaxQ]
-    uint16_t* cut;     // [kMaxQ]
-    float* r;          // [P]
-    uint16_t* ord;     // [P]
-    uint32_t* scratch; // [kBlock]
-    uint32_t* misc;    // [8]
+constexpr uint32_t kUnroll = 2;       // 16-byte row loads in flight per document and lane
+constexpr uint32_t kLanesPerDoc = 8;  // lanes sharing one row
+constexpr uint32_t kSumUnroll = 2;    // summary groups in flight per thread
+constexpr uint32_t kMaxSlots = 255;   // distinct query terms served by the u8 slot table
+
+template <int NT>
+struct SearchLds {
+    uint8_t* region;  // all-zero between queries: u8 slot table, or bitmap + prefix + values
+    uint32_t region_bytes;
+    double* qv;       // [256] value by slot (u8 mode), qv[0] = 0
+    QTable bq;        // bitmap mode, aliased on region
+    uint16_t* cut;    // [kMaxQ]
+    uint32_t* soff;   // [P + 1] summary offsets of the list's blocks, list-relative
+    float* r;         // [P] surviving blocks' summary scores (sorted in place)
+    uint16_t* ord;    // [P] their block index within the list
+    uint32_t* wp0;    // [kMaxW] window: first posting of each block
+    uint32_t* wlen;   // [kMaxW]  documents of each block
+    uint32_t* wst;    // [kMaxW + 1] prefix of wlen
+    uint32_t* scratch;
+    uint32_t* misc;
+    // union region
+    uint16_t* q_term;  // ingest [kMaxQ]
+    uint16_t* q_half;  // ingest [kMaxQ]
+    double* A;         // summary phase [P]
+    double* B;         // summary phase [P]
+    uint32_t* cdoc;    // gather phase [NT]
+    uint64_t* crs;     // [NT]
+    uint32_t* clen;    // [NT] row lengths
+    double* cacc;      // [NT]
+    uint8_t* cslot;    // [NT]
 };
 
-__device__ __forceinline__ uint8_t* bump(uint8_t*& p, size_t bytes) {
-    uint8_t* out = p;
-    p += (bytes + 15) & ~size_t(15);
-    return out;
+__host__ __device__ inline uint32_t r16u(uint64_t x) { return (uint32_t)((x + 15) & ~uint64_t(15)); }
+
+__host__ __device__ inline uint32_t region_bytes_for(uint32_t dim) {
+    const uint32_t nw = (dim + 63) / 64;
+    const uint32_t bitmap = r16u(8ull * nw) + r16u(2ull * nw) + r16u(4ull * kMaxQ);
+    const uint32_t table = r16u(dim);
+    return bitmap > table ? bitmap : table;
 }
 
-__global__ __launch_bounds__(kBlock) void k_search_v1(SearchArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int wave = tid / kWave;
-    const uint32_t qi = blockIdx.x;
-    const DevIdx& ix = a.ix;
-    const uint32_t nw = (ix.dim + 63u) / 64u;
-    const uint32_t P = a.sort_cap;
+template <int NT>
+__host__ __device__ inline size_t union_bytes(uint32_t P) {
+    size_t ingest = 2 * 2 * (size_t)kMaxQ + 32;
+    size_t summ = 2 * 8 * (size_t)P + 32;
+    size_t gath = (size_t)NT * (8 + 8 + 4 + 4 + 1) + 6 * 16;
+    size_t m = ingest > summ ? ingest : summ;
+    return m > gath ? m : gath;
+}
 
-    uint8_t* p = smem;
-    QTable q;
-    q.bits = (uint64_t*)bump(p, 8ull * nw);
-    q.pref = (uint16_t*)bump(p, 2ull * nw);
-    q.val = (float*)bump(p, 4ull * kMaxQ);
-    uint16_t* q_term = (uint16_t*)bump(p, 2ull * kMaxQ);
-    uint16_t* q_half = (uint16_t*)bump(p, 2ull * kMaxQ);
-    uint16_t* cut = (uint16_t*)bump(p, 2ull * kMaxQ);
-    float* r = (float*)bump(p, 4ull * P);
-    uint16_t* ord = (uint16_t*)bump(p, 2ull * P);
-    uint32_t* scratch = (uint32_t*)bump(p, 4ull * kBlock);
-    uint32_t* misc = (uint32_t*)bump(p, 4ull * 8);
-    TopK top;
-    top.hs[0] = (float*)bump(p, 4ull * a.k);
-    top.hs[1] = (float*)bump(p, 4ull * a.k);
-    top.hid[0] = (uint32_t*)bump(p, 4ull * a.k);
-    top.hid[1] = (uint32_t*)bump(p, 4ull * a.k);
-    top.cs = (float*)bump(p, 4ull * 2 * kBlock);
-    top.cid = (uint32_t*)bump(p, 4ull * 2 * kBlock);
-    top.flag = (uint32_t*)bump(p, 4ull * (kBlock + 32));
-    top.cur = 0;
+template <int NT>
+__device__ inline void carve_lds(uint8_t* base, uint32_t dim, uint32_t P, uint32_t k, SearchLds<NT>& L,
+                                 TopK<NT>& top) {
+    const uint32_t nw = (dim + 63) / 64;
+    uint8_t* p = base;
+    L.region_bytes = region_bytes_for(dim);
+    L.region = carve(p, L.region_bytes);
+    {
+        uint8_t* b = L.region;
+        L.bq.bits = (uint64_t*)carve(b, 8ull * nw);
+        L.bq.pref = (uint16_t*)carve(b, 2ull * nw);
+        L.bq.val = (float*)carve(b, 4ull * kMaxQ);
+    }
+    L.qv = (double*)carve(p, 8ull * 256);
+    L.cut = (uint16_t*)carve(p, 2ull * kMaxQ);
+    L.soff = (uint32_t*)carve(p, 4ull * (P + 1));
+    L.r = (float*)carve(p, 4ull * P);
+    L.ord = (uint16_t*)carve(p, 2ull * P);
+    L.wp0 = (uint32_t*)carve(p, 4ull * kMaxW);
+    L.wlen = (uint32_t*)carve(p, 4ull * kMaxW);
+    L.wst = (uint32_t*)carve(p, 4ull * (kMaxW + 1));
+    L.scratch = (uint32_t*)carve(p, 4ull * (NT / kWave + 8));
+    L.misc = (uint32_t*)carve(p, 4ull * 16);
+    top.s0 = (float*)carve(p, 4ull * k);
+    top.s1 = (float*)carve(p, 4ull * k);
+    top.i0 = (uint32_t*)carve(p, 4ull * k);
+    top.i1 = (uint32_t*)carve(p, 4ull * k);
+    top.cs = (float*)carve(p, 4ull * 2 * NT);
+    top.cid = (uint32_t*)carve(p, 4ull * 2 * NT);
+    top.scratch = L.scratch;
+    top.which = 0;
     top.hn = 0;
-    top.k = a.k;
+    top.k = k;
+    uint8_t* u = p;
+    uint8_t* q = u;
+    L.q_term = (uint16_t*)carve(q, 2ull * kMaxQ);
+    L.q_half = (uint16_t*)carve(q, 2ull * kMaxQ);
+    q = u;
+    L.A = (double*)carve(q, 8ull * P);
+    L.B = (double*)carve(q, 8ull * P);
+    q = u;
+    L.cacc = (double*)carve(q, 8ull * NT);
+    L.crs = (uint64_t*)carve(q, 8ull * NT);
+    L.cdoc = (uint32_t*)carve(q, 4ull * NT);
+    L.clen = (uint32_t*)carve(q, 4ull * NT);
+    L.cslot = (uint8_t*)carve(q, 1ull * NT);
+}
 
-    // ---------------------------------------------------------- ingest
-    const uint64_t q1 = min(a.q_ptr[qi + 1], a.q_nnz), q0 = min(a.q_ptr[qi], q1);
-    const uint64_t raw = q1 - q0;
-    const uint32_t nqe = (uint32_t)min<uint64_t>(raw, (uint64_t)kMaxQ);
-    for (uint32_t i = tid; i < nw; i += kBlock) q.bits[i] = 0ull;
-    if (tid < 8) misc[tid] = 0;
-    __syncthreads();
-    uint32_t st = (raw > (uint64_t)kMaxQ) ? 4u : 0u;
-    for (uint32_t j = tid; j < nqe; j += kBlock) {
-        const uint32_t w = a.q_words[q0 + j];
-        const uint32_t t = w & 0xFFFFu, h = w >> 16;
-        bool keep = true;
-        if (t >= ix.dim) { st |= 1u; keep = false; }
-        if (!half_ok(h)) { st |= 8u; keep = false; }
-        if (j > 0 && t <= (a.q_words[q0 + j - 1] & 0xFFFFu)) st |= 2u;
-        if (keep) {
-            const uint64_t bit = 1ull << (t & 63u);
-            const uint64_t old = atomicOr((unsigned long long*)&q.bits[t >> 6], (unsigned long long)bit);
-            if (old & bit) { st |= 2u; keep = false; }  // repeated term: first writer wins
+template <int NT>
+size_t search_smem_bytes_t(uint32_t dim, uint32_t P, uint32_t k) {
+    size_t s = region_bytes_for(dim);
+    s += r16u(8 * 256) + r16u(2 * kMaxQ);
+    s += r16u(4 * ((size_t)P + 1)) + r16u(4 * (size_t)P) + r16u(2 * (size_t)P);
+    s += 2 * r16u(4 * kMaxW) + r16u(4 * (kMaxW + 1)) + r16u(4 * (NT / kWave + 8)) + r16u(64);
+    s += 4 * r16u(4 * (size_t)k) + 2 * r16u(4 * 2 * (size_t)NT);
+    s += union_bytes<NT>(P);
+    return s;
+}
+
+// Query value of term t as fp64 (0 when absent): u8 slot table ...
+struct LookU8 {
+    const uint8_t* slot;
+    const double* qv;
+    __device__ __forceinline__ double operator()(uint32_t t) const { return qv[slot[t]]; }
+};
+
+// ... or membership bitmap with prefix counts (long queries).
+struct LookBits {
+    QTable q;
+    __device__ __forceinline__ double operator()(uint32_t t) const {
+        float v;
+        return q_lookup(q, t, v) ? (double)v : 0.0;
+    }
+};
+
+// One 16-byte group of 8 summary entries starting at entry eb: adds
+// sum(q) and sum(q * code) of the entries inside [S0, S1) to the LDS
+// accumulators of their blocks.
+template <int NT, typename Look>
+__device__ __forceinline__ void summary_group(const SearchLds<NT>& L, const Look& look, uint64_t eb, uint4 tv,
+                                              uint2 cv, uint64_t S0, uint64_t S1, uint32_t nb) {
+    const uint32_t tw[4] = {tv.x, tv.y, tv.z, tv.w};
+    const uint32_t lo = (uint32_t)((eb > S0 ? eb : S0) - S0);
+    uint32_t blo = 0, bhi = nb;  // block holding entry lo
+    while (bhi - blo > 1) {
+        const uint32_t mid = (blo + bhi) >> 1;
+        if (L.soff[mid] <= lo) blo = mid; else bhi = mid;
+    }
+    uint32_t blk = blo;
+    if (eb >= S0 && eb + 8 <= S1 && L.soff[blk + 1] >= lo + 8) {
+        // the whole group lies inside one block: straight-line
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (uint32_t e = 0; e < 8; ++e) {
+            const double qd = look((tw[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu);
+            const uint32_t code = ((e < 4 ? cv.x : cv.y) >> ((e & 3) * 8)) & 0xFFu;
+            sa += qd;
+            sb = fma(qd, (double)code, sb);  // exact: 11 x 8 bits
         }
-        q_term[j] = keep ? (uint16_t)t : (uint16_t)0xFFFFu;
-        q_half[j] = (uint16_t)h;
+        if (sa != 0.0) { atomicAdd(&L.A[blk], sa); atomicAdd(&L.B[blk], sb); }
+        return;
     }
-    if (st) atomicOr(&misc[0], st);
-    __syncthreads();
-    build_prefix(q.bits, q.pref, nw, scratch);
-    uint32_t nvalid_local = 0;
-    for (uint32_t j = tid; j < nqe; j += kBlock) {
-        const uint32_t t = q_term[j];
-        if (t == 0xFFFFu) continue;
-        const uint64_t w = q.bits[t >> 6];
-        const uint32_t slot = q.pref[t >> 6] + (uint32_t)__popcll(w & ((1ull << (t & 63u)) - 1ull));
-        q.val[slot] = half_bits_to_float(q_half[j]);
-        ++nvalid_local;
-    }
-    if (nvalid_local) atomicAdd(&misc[1], nvalid_local);
-    __syncthreads();
-    const uint32_t nvalid = misc[1];
-    const uint32_t ncut = (a.cut == 0 || a.cut > nvalid) ? nvalid : a.cut;
-    // cut order: value desc (positive fp16: bit order), then term asc
-    for (uint32_t j = tid; j < nqe; j += kBlock) {
-        const uint32_t t = q_term[j];
-        if (t == 0xFFFFu) continue;
-        const uint32_t h = q_half[j];
-        uint32_t rank = 0;
-        for (uint32_t i = 0; i < nqe; ++i) {
-            const uint32_t ti = q_term[i];
-            if (ti == 0xFFFFu) continue;
-            const uint32_t hi = q_half[i];
-            rank += (hi > h || (hi == h && ti < t)) ? 1u : 0u;
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (uint32_t e = 0; e < 8; ++e) {
+        if (eb + e < S0 || eb + e >= S1) continue;
+        const uint32_t rel = (uint32_t)(eb + e - S0);
+        while (L.soff[blk + 1] <= rel) {
+            if (sa != 0.0) { atomicAdd(&L.A[blk], sa); atomicAdd(&L.B[blk], sb); }
+            sa = 0.0; sb = 0.0;
+            ++blk;
         }
-        if (rank < ncut) cut[rank] = (uint16_t)t;
+        const double qd = look((tw[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu);
+        const uint32_t code = ((e < 4 ? cv.x : cv.y) >> ((e & 3) * 8)) & 0xFFu;
+        sa += qd;
+        sb = fma(qd, (double)code, sb);
+    }
+    if (sa != 0.0) { atomicAdd(&L.A[blk], sa); atomicAdd(&L.B[blk], sb); }
+}
+
+// Gather documents [0, tot) of the current window (slot s covers
+// [wst[s], wst[s+1]); big_off offsets the postings of a single oversized
+// block) and score them.  A thread per document fetches its posting and row
+// offsets; then groups of kLanesPerDoc lanes own whole rows, two documents
+// per group at a time, reading each row as 16-byte aligned groups of 4 words
+// (words outside the row are replaced by 0, which adds exactly 0) with
+// kUnroll loads per document in flight, and reduce with shuffles.  On return
+// cacc[t] is the exact score of document t (fp64) and clen[t] its number of
+// nonzeros.  Every thread calls it; it ends with a barrier.
+template <int NT, typename Look>
+__device__ inline void gather_and_score(const DevIdx& ix, const SearchLds<NT>& L, const Look& look, uint32_t tot,
+                                        uint32_t nwb, uint32_t big_off) {
+    const int tid = threadIdx.x;
+    if ((uint32_t)tid < tot) {
+        uint32_t s = 0;
+        while (s + 1 < nwb && L.wst[s + 1] <= (uint32_t)tid) ++s;
+        const uint32_t p = L.wp0[s] + big_off + ((uint32_t)tid - L.wst[s]);
+        const uint32_t d = ix.postings[p];
+        const uint64_t rs = ix.row_ptr[d], re = ix.row_ptr[d + 1];
+        L.cdoc[tid] = d;
+        L.crs[tid] = rs;
+        L.clen[tid] = (uint32_t)(re - rs);
+        L.cslot[tid] = (uint8_t)s;
     }
     __syncthreads();
+    constexpr uint32_t G = kLanesPerDoc, NG = NT / kLanesPerDoc;
+    const uint32_t grp = (uint32_t)tid / G, gl = (uint32_t)tid % G;
+    for (uint32_t base = grp; base < tot; base += 2 * NG) {
+        uint64_t g0[2];
+        uint32_t ng[2], head[2], len[2];
+        double acc[2] = {0.0, 0.0};
+#pragma unroll
+        for (uint32_t h = 0; h < 2; ++h) {
+            const uint32_t t = base + h * NG;
+            const uint64_t rs = t < tot ? L.crs[t] : 0;
+            len[h] = t < tot ? L.clen[t] : 0;
+            g0[h] = rs >> 2;
+            head[h] = (uint32_t)(rs & 3);  // row start inside its first group
+            ng[h] = len[h] ? (uint32_t)(((rs + len[h] + 3) >> 2) - g0[h]) : 0u;
+        }
+        for (uint32_t k = gl; k < ng[0] || k < ng[1]; k += kUnroll * G) {
+            uint4 w[2][kUnroll];
+#pragma unroll
+            for (uint32_t h = 0; h < 2; ++h)
+#pragma unroll
+                for (uint32_t u = 0; u < kUnroll; ++u)
+                    w[h][u] = (k + u * G < ng[h]) ? *(const uint4*)(ix.words + ((g0[h] + k + u * G) << 2))
+                                                 : make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (uint32_t h = 0; h < 2; ++h)
+#pragma unroll
+                for (uint32_t u = 0; u < kUnroll; ++u) {
+                    // position of the group's first word relative to the row start
+                    const int32_t rel = (int32_t)((k + u * G) * 4u) - (int32_t)head[h];
+                    const uint32_t ww[4] = {w[h][u].x, w[h][u].y, w[h][u].z, w[h][u].w};
+#pragma unroll
+                    for (uint32_t e = 0; e < 4; ++e) {
+                        const int32_t at = rel + (int32_t)e;
+                        const uint32_t x = (at >= 0 && at < (int32_t)len[h]) ? ww[e] : 0u;
+                        acc[h] = fma(look(x & 0xFFFFu), (double)half_bits_to_float(x >> 16), acc[h]);
+                    }
+                }
+        }
+        acc[0] = group_sum<double, G>(acc[0]);
+        acc[1] = group_sum<double, G>(acc[1]);
+        if (gl == 0) {
+            if (base < tot) L.cacc[base] = acc[0];
+            if (base + NG < tot) L.cacc[base + NG] = acc[1];
+        }
+    }
+    __syncthreads();
+}
 
-    // counters (thread 0 keeps the uniform ones)
-    uint64_t c_sum = 0, c_blocks = 0, c_eval = 0, c_docs = 0, c_tests = 0;
-    uint64_t c_nnz = 0;  // per thread, reduced at the end
+// Fold the gathered documents of window slot `slot` (all of them when
+// slot < 0) into the top-k.  Every thread calls it.
+template <int NT>
+__device__ inline void fold_slot(const SearchLds<NT>& L, TopK<NT>& top, uint32_t tot, int slot, uint64_t& c_nnz) {
+    const int tid = threadIdx.x;
+    bool cand = false;
+    float sc = 0.0f;
+    uint32_t d = 0;
+    if ((uint32_t)tid < tot && (slot < 0 || L.cslot[tid] == (uint32_t)slot)) {
+        sc = (float)L.cacc[tid];
+        d = L.cdoc[tid];
+        c_nnz += L.clen[tid];
+        cand = top.admits(sc, d);
+    }
+    uint32_t nc;
+    const uint32_t at = block_exscan<NT>(cand ? 1u : 0u, L.scratch, &nc);
+    if (cand) { top.cs[at] = sc; top.cid[at] = d; }
+    __syncthreads();
+    if (nc) top.merge(nc);
+}
 
+struct Counters {
+    uint64_t sum = 0, blocks = 0, eval = 0, docs = 0, tests = 0, nnz = 0;
+};
+
+// Steps 2a-2c for every cut list of query qi.
+template <int NT, typename Look>
+__device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>& top, const Look& look, uint32_t qi,
+                          uint32_t ncut, Counters& C) {
+    const int tid = threadIdx.x;
+    const DevIdx& ix = a.ix;
+    const uint32_t W = a.window;
     for (uint32_t ci = 0; ci < ncut; ++ci) {
-        const uint32_t t = cut[ci];
+        const uint32_t t = L.cut[ci];
         const uint32_t b0 = ix.list_off[t], b1 = ix.list_off[t + 1];
         const uint32_t nb = b1 - b0;
         if (nb == 0) {
             if (a.prefix && tid == 0 && ci < a.prefix_stride) a.prefix[(size_t)qi * a.prefix_stride + ci] = 0;
             continue;
         }
-        c_sum += ix.blk_sum_off[b1] - ix.blk_sum_off[b0];
-        c_blocks += nb;
-        // ------------------------------------------ a. summary scores
-        for (uint32_t bl = wave; bl < nb; bl += kBlock / kWave) {
-            const uint32_t b = b0 + bl;
-            const uint64_t s0 = ix.blk_sum_off[b], s1 = ix.blk_sum_off[b + 1];
-            double A = 0.0, B = 0.0;
-            for (uint64_t e = s0 + lane; e < s1; e += kWave) {
-                float qv;
-                if (q_lookup(q, ix.sum_term[e], qv)) {
-                    A += (double)qv;
-                    B += (double)(qv * (float)ix.sum_code[e]);  // exact: 11 x 8 bits
+        // ---------------------------------------- a. summary scores
+        const uint64_t S0 = ix.blk_sum_off[b0], S1 = ix.blk_sum_off[b1];
+        C.sum += S1 - S0;
+        C.blocks += nb;
+        for (uint32_t i = tid; i <= nb; i += NT) L.soff[i] = (uint32_t)(ix.blk_sum_off[b0 + i] - S0);
+        for (uint32_t i = tid; i < nb; i += NT) { L.A[i] = 0.0; L.B[i] = 0.0; }
+        __syncthreads();
+        const uint64_t gend = (S1 + 7) >> 3;
+        for (uint64_t g0 = (S0 >> 3) + tid; g0 < gend; g0 += (uint64_t)NT * kSumUnroll) {
+            uint4 tv[kSumUnroll];
+            uint2 cv[kSumUnroll];
+#pragma unroll
+            for (uint32_t u = 0; u < kSumUnroll; ++u) {
+                const uint64_t g = g0 + (uint64_t)u * NT;
+                if (g < gend) {
+                    tv[u] = *(const uint4*)(ix.sum_term + (g << 3));
+                    cv[u] = *(const uint2*)(ix.sum_code + (g << 3));
                 }
             }
-            A = wave_sum(A);
-            B = wave_sum(B);
-            if (lane == 0) r[bl] = (float)((double)ix.blk_m[b] * A + (double)ix.blk_delta[b] * B);
+#pragma unroll
+            for (uint32_t u = 0; u < kSumUnroll; ++u) {
+                const uint64_t g = g0 + (uint64_t)u * NT;
+                if (g < gend) summary_group<NT, Look>(L, look, g << 3, tv[u], cv[u], S0, S1, nb);
+            }
+        }
+        __syncthreads();
+        // ---------------------------------------- b. prefilter + sort
+        const bool full0 = top.full();
+        const double hmin0 = full0 ? (double)top.min_score() : 0.0;
+        uint32_t nsurv = 0;
+        for (uint32_t c = 0; c < nb; c += NT) {
+            const uint32_t i = c + tid;
+            float rv = 0.0f;
+            bool keep = false;
+            if (i < nb) {
+                rv = (float)((double)ix.blk_m[b0 + i] * L.A[i] + (double)ix.blk_delta[b0 + i] * L.B[i]);
+                keep = !(full0 && (double)rv * (double)a.hf < hmin0);
+            }
+            uint32_t cnt;
+            const uint32_t at = block_exscan<NT>(keep ? 1u : 0u, L.scratch, &cnt);
+            if (keep) { L.r[nsurv + at] = rv; L.ord[nsurv + at] = (uint16_t)i; }
+            nsurv += cnt;
         }
         uint32_t Pl = 2;
-        while (Pl < nb) Pl <<= 1;
-        for (uint32_t i = tid; i < Pl; i += kBlock) {
-            if (i >= nb) r[i] = -INFINITY;
-            ord[i] = (uint16_t)i;
-        }
+        while (Pl < nsurv) Pl <<= 1;
+        for (uint32_t i = nsurv + tid; i < Pl; i += NT) { L.r[i] = -INFINITY; L.ord[i] = 0xFFFFu; }
         __syncthreads();
-        // ------------------------------------------ b. bitonic sort
-        for (uint32_t kk = 2; kk <= Pl; kk <<= 1) {
-            for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = tid; i < Pl; i += kBlock) {
-                    const uint32_t l = i ^ j;
-                    if (l > i) {
-                        const float ri = r[i], rl = r[l];
-                        const uint32_t oi = ord[i], ol = ord[l];
-                        const bool l_first = rl > ri || (rl == ri && ol < oi);
-                        const bool up = (i & kk) == 0;
-                        if (up ? l_first : !l_first) {
-                            r[i] = rl; r[l] = ri; ord[i] = (uint16_t)ol; ord[l] = (uint16_t)oi;
+        if (nsurv > 1) {
+            for (uint32_t kk = 2; kk <= Pl; kk <<= 1) {
+                for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                    for (uint32_t i = tid; i < Pl; i += NT) {
+                        const uint32_t l = i ^ jj;
+                        if (l > i) {
+                            const float ri = L.r[i], rl = L.r[l];
+                            const uint32_t oi = L.ord[i], ol = L.ord[l];
+                            const bool l_first = rl > ri || (rl == ri && ol < oi);
+                            if (((i & kk) == 0) ? l_first : !l_first) {
+                                L.r[i] = rl; L.r[l] = ri; L.ord[i] = (uint16_t)ol; L.ord[l] = (uint16_t)oi;
+                            }
                         }
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
         }
-        // ------------------------------------------ c. traversal
-        uint32_t pos = 0;
-        for (; pos < nb; ++pos) {
-            const float rj = r[pos];
-            if (ord[pos] >= nb) break;  // only padding left (cannot happen for finite scores)
-            const uint32_t b = b0 + ord[pos];
-            if (top.hn == top.k) {
-                ++c_tests;
-                if ((double)rj * (double)a.hf < (double)top.hs[top.cur][top.k - 1]) break;
+        // ---------------------------------------- c. traversal
+        uint32_t pos = 0, evaluated = 0;
+        bool stop = false;
+        while (pos < nsurv && !stop) {
+            if ((uint32_t)tid < W && pos + tid < nsurv) {
+                const uint32_t b = b0 + L.ord[pos + tid];
+                const uint32_t p0 = ix.blk_post_off[b];
+                L.wp0[tid] = p0;
+                L.wlen[tid] = ix.blk_post_off[b + 1] - p0;
             }
-            const uint32_t p0 = ix.blk_post_off[b], p1 = ix.blk_post_off[b + 1];
-            ++c_eval;
-            c_docs += p1 - p0;
-            for (uint32_t c0 = p0; c0 < p1; c0 += kBlock / 16) {
-                const uint32_t g = tid >> 4, gl = tid & 15u;
-                const uint32_t pp = c0 + g;
-                double acc = 0.0;
-                uint32_t d = 0;
-                if (pp < p1) {
-                    d = ix.postings[pp];
-                    const uint64_t rs = ix.row_ptr[d], re = ix.row_ptr[d + 1];
-                    if (gl == 0) c_nnz += re - rs;
-                    for (uint64_t e = rs + gl; e < re; e += 16) {
-                        const uint32_t w = ix.words[e];
-                        float qv;
-                        if (q_lookup(q, w & 0xFFFFu, qv)) acc += (double)(qv * half_bits_to_float(w >> 16));
-                    }
+            __syncthreads();
+            uint32_t nwb = 0, tot = 0;
+            for (uint32_t s = 0; s < W && pos + s < nsurv; ++s) {
+                const uint32_t len = L.wlen[s];
+                if (s > 0 && tot + len > (uint32_t)NT) break;
+                tot += len;
+                ++nwb;
+            }
+            if (tot > (uint32_t)NT) {
+                // a single block larger than a chunk: evaluated alone
+                if (top.full()) {
+                    ++C.tests;
+                    if ((double)L.r[pos] * (double)a.hf < (double)top.min_score()) { stop = true; break; }
                 }
-                acc = group_sum<double, 16>(acc);
-                if (gl == 0 && pp < p1) { top.cs[g] = (float)acc; top.cid[g] = d; }
+                ++evaluated;
+                C.docs += tot;
+                for (uint32_t c0 = 0; c0 < tot; c0 += NT) {
+                    const uint32_t n = min((uint32_t)NT, tot - c0);
+                    if (tid == 0) { L.wst[0] = 0; L.wst[1] = n; }
+                    __syncthreads();
+                    gather_and_score<NT, Look>(ix, L, look, n, 1, c0);
+                    fold_slot<NT>(L, top, n, -1, C.nnz);
+                }
+                ++pos;
                 __syncthreads();
-                top.merge(min(p1 - c0, (uint32_t)(kBlock / 16)));
+                continue;
             }
+            if (tid == 0) {
+                uint32_t run = 0;
+                for (uint32_t s = 0; s < nwb; ++s) { L.wst[s] = run; run += L.wlen[s]; }
+                L.wst[nwb] = run;
+            }
+            __syncthreads();
+            gather_and_score<NT, Look>(ix, L, look, tot, nwb, 0);
+            for (uint32_t s = 0; s < nwb; ++s) {
+                if (top.full()) {
+                    ++C.tests;
+                    if ((double)L.r[pos + s] * (double)a.hf < (double)top.min_score()) { stop = true; break; }
+                }
+                ++evaluated;
+                C.docs += L.wlen[s];
+                fold_slot<NT>(L, top, tot, (int)s, C.nnz);
+            }
+            pos += stop ? 0u : nwb;
+            __syncthreads();
         }
+        if (!stop && nsurv < nb) ++C.tests;  // the first dropped block ends the list
         if (a.prefix && tid == 0 && ci < a.prefix_stride)
-            a.prefix[(size_t)qi * a.prefix_stride + ci] = (uint16_t)min(pos, 65535u);
-        __syncthreads();  // r/ord are rewritten by the next list
+            a.prefix[(size_t)qi * a.prefix_stride + ci] = (uint16_t)min(evaluated, 65535u);
+        C.eval += evaluated;
+        __syncthreads();
     }
+}
 
-    // ------------------------------------------------------------ output
-    for (uint32_t i = tid; i < a.k; i += kBlock) {
-        const bool have = i < top.hn;
-        a.out_ids[(size_t)qi * a.k + i] = have ? top.hid[top.cur][i] : 0xFFFFFFFFu;
-        a.out_scores[(size_t)qi * a.k + i] = have ? top.hs[top.cur][i] : -INFINITY;
-    }
-    if (a.prefix)
-        for (uint32_t i = ncut + tid; i < a.prefix_stride; i += kBlock) a.prefix[(size_t)qi * a.prefix_stride + i] = 0;
-    if (a.counters) {
-        // block reduction of c_nnz
-        unsigned long long v = wave_sum((unsigned long long)c_nnz);
+template <int NT>
+__global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x;
+    const DevIdx& ix = a.ix;
+    const uint32_t nw = (ix.dim + 63u) / 64u;
+    SearchLds<NT> L;
+    TopK<NT> top;
+    carve_lds<NT>(smem, ix.dim, a.sort_cap, a.k, L, top);
+    for (uint32_t i = tid; i < L.region_bytes / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
+    if (tid == 0) L.qv[0] = 0.0;
+    __syncthreads();
+
+    for (;;) {
+        // ------------------------------------------------ next query
+        if (tid == 0) L.misc[15] = atomicAdd(a.queue, 1u);
         __syncthreads();
-        if (lane == 0) ((unsigned long long*)scratch)[wave] = v;
+        const uint32_t qi = L.misc[15];
+        if (qi >= a.nq) break;
+        top.which = 0;
+        top.hn = 0;
+
+        // ---------------------------------------------------------- ingest
+        const uint64_t q1 = min(a.q_ptr[qi + 1], a.q_nnz), q0 = min(a.q_ptr[qi], q1);
+        const uint64_t raw = q1 - q0;
+        const uint32_t nqe = (uint32_t)min<uint64_t>(raw, (uint64_t)kMaxQ);
+        if (tid < 8) L.misc[tid] = 0;
         __syncthreads();
-        if (tid == 0) {
-            unsigned long long tot = 0;
-            for (int w = 0; w < kBlock / kWave; ++w) tot += ((unsigned long long*)scratch)[w];
-            uint64_t* c = a.counters + (size_t)qi * 8;
-            c[0] = c_sum; c[1] = c_blocks; c[2] = c_eval; c[3] = c_docs; c[4] = tot; c[5] = c_tests;
-            c[6] = misc[0]; c[7] = ncut;
+        uint32_t st = (raw > (uint64_t)kMaxQ) ? 4u : 0u;
+        for (uint32_t j = tid; j < nqe; j += NT) {
+            const uint32_t w = a.q_words[q0 + j];
+            const uint32_t t = w & 0xFFFFu, h = w >> 16;
+            bool keep = true;
+            if (t >= ix.dim) { st |= 1u; keep = false; }
+            if (!half_ok(h)) { st |= 8u; keep = false; }
+            if (j > 0 && t <= (a.q_words[q0 + j - 1] & 0xFFFFu)) st |= 2u;
+            if (keep) {
+                const uint64_t bit = 1ull << (t & 63u);
+                const uint64_t old = atomicOr((unsigned long long*)&L.bq.bits[t >> 6], (unsigned long long)bit);
+                if (old & bit) { st |= 2u; keep = false; }  // repeated term: first writer wins
+            }
+            L.q_term[j] = keep ? (uint16_t)t : (uint16_t)0xFFFFu;
+            L.q_half[j] = (uint16_t)h;
         }
+        if (st) atomicOr(&L.misc[0], st);
+        __syncthreads();
+        build_prefix<NT>(L.bq.bits, L.bq.pref, nw, L.scratch);
+        uint32_t nvalid_local = 0;
+        for (uint32_t j = tid; j < nqe; j += NT) nvalid_local += L.q_term[j] != 0xFFFFu ? 1u : 0u;
+        if (nvalid_local) atomicAdd(&L.misc[1], nvalid_local);
+        __syncthreads();
+        const uint32_t nvalid = L.misc[1];
+        const bool u8mode = nvalid <= kMaxSlots;
+        const uint32_t ncut = (a.cut == 0 || a.cut > nvalid) ? nvalid : a.cut;
+        // slot of every valid entry (1-based rank of its term)
+        uint32_t my_slot[kMaxQ / NT];
+#pragma unroll
+        for (uint32_t r = 0; r < kMaxQ / NT; ++r) {
+            const uint32_t j = tid + r * NT;
+            my_slot[r] = 0;
+            if (j >= nqe) continue;
+            const uint32_t t = L.q_term[j];
+            if (t == 0xFFFFu) continue;
+            const uint64_t w = L.bq.bits[t >> 6];
+            const uint32_t slot = L.bq.pref[t >> 6] + (uint32_t)__popcll(w & ((1ull << (t & 63u)) - 1ull));
+            my_slot[r] = slot + 1;
+            if (u8mode) L.qv[slot + 1] = (double)half_bits_to_float(L.q_half[j]);
+        }
+        // cut order: value desc (positive fp16: bit order), then term asc
+        for (uint32_t j = tid; j < nqe; j += NT) {
+            const uint32_t t = L.q_term[j];
+            if (t == 0xFFFFu) continue;
+            const uint32_t h = L.q_half[j];
+            uint32_t rank = 0;
+            for (uint32_t i = 0; i < nqe; ++i) {
+                const uint32_t ti = L.q_term[i];
+                const uint32_t hi = L.q_half[i];
+                rank += (ti != 0xFFFFu && (hi > h || (hi == h && ti < t))) ? 1u : 0u;
+            }
+            if (rank < ncut) L.cut[rank] = (uint16_t)t;
+        }
+        const uint32_t status = L.misc[0];
+        __syncthreads();
+        if (u8mode) {
+            // bitmap + prefix -> slot table
+            for (uint32_t i = tid; i < (10 * nw + 15) / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
+            __syncthreads();
+#pragma unroll
+            for (uint32_t r = 0; r < kMaxQ / NT; ++r)
+                if (my_slot[r]) L.region[L.q_term[tid + r * NT]] = (uint8_t)my_slot[r];
+        } else {
+#pragma unroll
+            for (uint32_t r = 0; r < kMaxQ / NT; ++r)
+                if (my_slot[r]) L.bq.val[my_slot[r] - 1] = half_bits_to_float(L.q_half[tid + r * NT]);
+        }
+        __syncthreads();
+
+        Counters C;
+        if (u8mode) {
+            LookU8 look{L.region, L.qv};
+            run_lists<NT, LookU8>(a, L, top, look, qi, ncut, C);
+        } else {
+            LookBits look{L.bq};
+            run_lists<NT, LookBits>(a, L, top, look, qi, ncut, C);
+        }
+
+        // ------------------------------------------------------------ output
+        {
+            const float* H = top.hs();
+            const uint32_t* I = top.hid();
+            for (uint32_t i = tid; i < a.k; i += NT) {
+                const bool have = i < top.hn;
+                a.out_ids[(size_t)qi * a.k + i] = have ? I[i] : 0xFFFFFFFFu;
+                a.out_scores[(size_t)qi * a.k + i] = have ? H[i] : -INFINITY;
+            }
+        }
+        if (a.prefix)
+            for (uint32_t i = ncut + tid; i < a.prefix_stride; i += NT) a.prefix[(size_t)qi * a.prefix_stride + i] = 0;
+        if (a.counters) {
+            const unsigned long long v = wave_sum((unsigned long long)C.nnz);
+            unsigned long long* red = (unsigned long long*)L.crs;  // union region is free here
+            if ((tid & (kWave - 1)) == 0) red[tid / kWave] = v;
+            __syncthreads();
+            if (tid == 0) {
+                unsigned long long tot = 0;
+                for (int w = 0; w < NT / kWave; ++w) tot += red[w];
+                uint64_t* c = a.counters + (size_t)qi * 8;
+                c[0] = C.sum; c[1] = C.blocks; c[2] = C.eval; c[3] = C.docs; c[4] = tot; c[5] = C.tests;
+                c[6] = status; c[7] = ncut;
+            }
+        }
+        // restore the all-zero region
+        if (u8mode) {
+            for (uint32_t j = tid; j < nqe; j += NT) {
+                const uint32_t t = a.q_words[q0 + j] & 0xFFFFu;
+                if (t < ix.dim) L.region[t] = 0;
+            }
+        } else {
+            for (uint32_t i = tid; i < L.region_bytes / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
+        }
+        __syncthreads();
     }
 }
 
-size_t search_v1_smem_bytes(uint32_t dim, uint32_t sort_cap, uint32_t k) {
-    auto r16 = [](size_t x) { return (x + 15) & ~size_t(15); };
-    size_t nw = (dim + 63) / 64;
-    size_t s = 0;
-    s += r16(8 * nw) + r16(2 * nw) + r16(4 * kMaxQ) + 3 * r16(2 * kMaxQ);
-    s += r16(4 * (size_t)sort_cap) + r16(2 * (size_t)sort_cap) + r16(4 * kBlock) + r16(32);
-    s += 4 * r16(4 * (size_t)k) + 2 * r16(4 * 2 * kBlock) + r16(4 * (kBlock + 32));
-    return s;
+__global__ void k_reset_queue(uint32_t* queue) {
+    if (threadIdx.x == 0) *queue = 0;
 }
 
-hipError_t launch_search_v1(const SearchArgs& a, uint32_t nq, size_t smem, hipStream_t stream) {
-    if (nq == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_search_v1, dim3(nq), dim3(kBlock), smem, stream, a);
+size_t search_smem_bytes(uint32_t nt, uint32_t dim, uint32_t sort_cap, uint32_t k) {
+    return nt == 512 ? search_smem_bytes_t<512>(dim, sort_cap, k) : search_smem_bytes_t<256>(dim, sort_cap, k);
+}
+
+int search_blocks_per_cu(uint32_t nt, size_t smem) {
+    int n = 0;
+    hipError_t e = nt == 512 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<512>, 512, smem)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<256>, 256, smem);
+    return e == hipSuccess ? n : 0;
+}
+
+hipError_t launch_search(const SearchArgs& a, uint32_t nt, uint32_t grid, size_t smem, hipStream_t stream) {
+    if (a.nq == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, stream, a.queue);
+    if (nt == 512)
+        hipLaunchKernelGGL(k_search<512>, dim3(grid), dim3(512), smem, stream, a);
+    else
+        hipLaunchKernelGGL(k_search<256>, dim3(grid), dim3(256), smem, stream, a);
     return hipGetLastError();
 }
 

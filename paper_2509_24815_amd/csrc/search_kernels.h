@@ -11,16 +11,20 @@ namespace seismic_dev {
 
 constexpr uint32_t kMaxQ = 1024;       // query nonzeros handled per query (SEISMIC_MAX_QUERY_NNZ)
 constexpr uint32_t kMaxSortCap = 8192; // largest number of blocks in one list
+constexpr uint32_t kMaxW = 32;         // largest speculation window (blocks)
 
 struct SearchArgs {
     DevIdx ix;
     const uint64_t* q_ptr;
     const uint32_t* q_words;
-    uint64_t q_nnz;  // length of q_words: row offsets are clamped to it
+    uint64_t q_nnz;     // length of q_words: row offsets are clamped to it
+    uint32_t nq;
     uint32_t k;
     uint32_t cut;
     float hf;
     uint32_t sort_cap;  // power of two >= the largest list's block count
+    uint32_t window;    // speculation window W in blocks, 1..kMaxW
+    uint32_t* queue;    // device counter handing out queries (reset by the launch)
     uint32_t* out_ids;
     float* out_scores;
     uint16_t* prefix;
@@ -28,8 +32,10 @@ struct SearchArgs {
     uint64_t* counters;
 };
 
-size_t search_v1_smem_bytes(uint32_t dim, uint32_t sort_cap, uint32_t k);
-hipError_t launch_search_v1(const SearchArgs& a, uint32_t nq, size_t smem, hipStream_t stream);
+// nt = threads per workgroup (256 or 512); grid = number of persistent workgroups.
+size_t search_smem_bytes(uint32_t nt, uint32_t dim, uint32_t sort_cap, uint32_t k);
+hipError_t launch_search(const SearchArgs& a, uint32_t nt, uint32_t grid, size_t smem, hipStream_t stream);
+int search_blocks_per_cu(uint32_t nt, size_t smem);  // resident workgroups per CU (0 on error)
 
 // Exact search over a full inverted index (term -> doc-ascending postings).
 struct ExactArgs {
