@@ -161,8 +161,34 @@ typedef struct {
     uint32_t reserved;
 } seismic_launch_config;
 
+/* set_config applies cfg to every batch-size bucket; get_config returns the
+   shape used for a batch of n_queries queries. */
 int seismic_workspace_set_config(seismic_workspace* ws, const seismic_launch_config* cfg);
-int seismic_workspace_get_config(const seismic_workspace* ws, seismic_launch_config* cfg);
+int seismic_workspace_get_config(const seismic_workspace* ws, uint32_t n_queries, seismic_launch_config* cfg);
+
+/* One candidate launch shape and its mean time per search_batch call. */
+typedef struct {
+    seismic_launch_config cfg;
+    float ms;
+    uint32_t reserved;
+} seismic_tune_result;
+
+/*
+ * Autotuner for the persistent search kernel.  Times seismic_search_batch
+ * on this batch under every launch shape that fits the device (threads
+ * 256/512 x window 1/2/4/8/16 x resident workgroups per CU 1..max), one
+ * warm-up and `reps` timed calls each (HIP events on `stream`; the call
+ * waits for the stream), checks that every shape returns the same ids and
+ * scores (EHIP-free mismatch => ESTATE), and stores the fastest shape for
+ * the batch-size bucket of queries->n_rows (buckets: <= 64, <= 512, <= 4096,
+ * larger).  out_ids/out_scores are caller device buffers [n_rows * k] that
+ * end up holding the results; results[0..max_results) (nullable) receive
+ * every candidate's timing, *n_results their count.  queries must be
+ * device resident.
+ */
+int seismic_autotune(const seismic_index* index, seismic_workspace* ws, const seismic_csr* queries,
+                     const seismic_search_params* params, uint32_t* out_ids, float* out_scores, uint32_t reps,
+                     seismic_tune_result* results, uint32_t max_results, uint32_t* n_results, void* stream);
 
 /*
  * Algorithm 2 (kappa = 0) for a batch of queries, asynchronously on stream.

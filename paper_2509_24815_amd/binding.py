@@ -50,6 +50,10 @@ class LaunchConfig(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("cfg", LaunchConfig), ("ms", ctypes.c_float), ("reserved", ctypes.c_uint32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("prefix", ctypes.c_void_p), ("prefix_stride", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("counters", ctypes.c_void_p)]
@@ -79,7 +83,8 @@ def load():
         "seismic_workspace_create": ([vp, u32, u32, P(vp)], i32),
         "seismic_workspace_free": ([vp], None),
         "seismic_workspace_set_config": ([vp, P(LaunchConfig)], i32),
-        "seismic_workspace_get_config": ([vp, P(LaunchConfig)], i32),
+        "seismic_workspace_get_config": ([vp, u32, P(LaunchConfig)], i32),
+        "seismic_autotune": ([vp, vp, P(Csr), P(SearchParams), vp, vp, u32, vp, u32, P(u32), vp], i32),
         "seismic_search_batch": ([vp, vp, P(Csr), P(SearchParams), vp, vp, P(Stats), vp], i32),
         "exact_topk": ([vp, P(Csr), u32, vp, vp, vp], i32),
     }
@@ -189,10 +194,23 @@ def seismic_workspace_set_config(ws, threads: int = 256, blocks_per_cu: int = 0,
     _check(load().seismic_workspace_set_config(ws, ctypes.byref(c)))
 
 
-def seismic_workspace_get_config(ws) -> dict:
+def seismic_workspace_get_config(ws, n_queries: int) -> dict:
     c = LaunchConfig()
-    _check(load().seismic_workspace_get_config(ws, ctypes.byref(c)))
+    _check(load().seismic_workspace_get_config(ws, n_queries, ctypes.byref(c)))
     return {"threads": c.threads, "blocks_per_cu": c.blocks_per_cu, "window": c.window}
+
+
+def seismic_autotune(handle, ws, queries: Csr, k: int, query_cut: int, heap_factor: float, out_ids, out_scores,
+                     reps: int = 3, stream=None, max_results: int = 256):
+    """Time every launch shape on this batch, keep the fastest for its
+    batch-size bucket; returns the list of (config, ms)."""
+    p = SearchParams(k, query_cut, heap_factor, 0)
+    res = (TuneResult * max_results)()
+    n = ctypes.c_uint32(0)
+    _check(load().seismic_autotune(handle, ws, ctypes.byref(queries), ctypes.byref(p), _ptr(out_ids), _ptr(out_scores),
+                                   reps, res, max_results, ctypes.byref(n), _stream_handle(stream)))
+    return [({"threads": r.cfg.threads, "blocks_per_cu": r.cfg.blocks_per_cu, "window": r.cfg.window}, r.ms)
+            for r in res[:n.value]]
 
 
 def seismic_search_batch(handle, ws, queries: Csr, k: int, query_cut: int, heap_factor: float,

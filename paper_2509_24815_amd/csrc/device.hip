@@ -100,12 +100,14 @@ int grow(void** p, size_t& cap, size_t need, size_t elem) {
 
 }  // namespace
 
+constexpr int kBuckets = 4;  // batch-size buckets of the launch configuration
+
 struct seismic_workspace {
     const seismic_index* index = nullptr;
     int device = -1;
     uint32_t max_queries = 0, max_k = 0;
     int n_cu = 0;
-    seismic_launch_config cfg{256, 0, 8, 0};
+    seismic_launch_config cfg[kBuckets];
     uint32_t* queue = nullptr;  // device counter of the persistent search kernel
     uint64_t* q_ptr = nullptr;  // staging for host-resident queries
     uint32_t* q_words = nullptr;
@@ -114,6 +116,8 @@ struct seismic_workspace {
 
 namespace {
 
+int bucket_of(uint64_t nq) { return nq <= 64 ? 0 : nq <= 512 ? 1 : nq <= 4096 ? 2 : 3; }
+
 int check_config(const seismic_workspace* ws, const seismic_launch_config* c) {
     if (c->threads != 256 && c->threads != 512) return fail(SEISMIC_EINVAL, "config: threads must be 256 or 512");
     if (c->window < 1 || c->window > seismic_dev::kMaxW)
@@ -121,6 +125,50 @@ int check_config(const seismic_workspace* ws, const seismic_launch_config* c) {
     size_t smem = seismic_dev::search_smem_bytes(c->threads, ws->index->h.dim, ws->index->dev->sort_cap, ws->max_k);
     if (smem > ws->index->dev->smem_limit)
         return fail(SEISMIC_EINVAL, "config: %zu bytes of LDS needed, the device allows %zu", smem, ws->index->dev->smem_limit);
+    return SEISMIC_OK;
+}
+
+int check_params(const seismic_index* index, const seismic_workspace* ws, const seismic_csr* queries,
+                 const seismic_search_params* params) {
+    if (!index->dev) return fail(SEISMIC_ESTATE, "search: index is not on a device");
+    if (ws->index != index) return fail(SEISMIC_EINVAL, "search: workspace belongs to another index");
+    if (params->k < 1 || params->k > ws->max_k) return fail(SEISMIC_EINVAL, "search: k = %u outside [1, %u]", params->k, ws->max_k);
+    if (!(params->heap_factor > 0.0f)) return fail(SEISMIC_EINVAL, "search: heap_factor must be > 0");
+    if (params->flags != 0) return fail(SEISMIC_EINVAL, "search: unknown flags");
+    if (queries->dim != index->h.dim) return fail(SEISMIC_EINVAL, "search: query dim %u != index dim %u", queries->dim, index->h.dim);
+    if (queries->n_rows > ws->max_queries)
+        return fail(SEISMIC_EINVAL, "search: %llu queries exceed the workspace (%u)", (unsigned long long)queries->n_rows, ws->max_queries);
+    return SEISMIC_OK;
+}
+
+// Enqueue one search of device-resident rows with launch shape cfg.
+int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64_t* q_ptr, const uint32_t* q_words,
+                 uint64_t nq, uint64_t nnz, const seismic_search_params* params, uint32_t* out_ids, float* out_scores,
+                 const seismic_stats* stats, const seismic_launch_config& cfg, hipStream_t st) {
+    seismic_dev::SearchArgs a{};
+    a.ix = index->dev->view;
+    a.q_ptr = q_ptr;
+    a.q_words = q_words;
+    a.q_nnz = nnz;
+    a.k = params->k;
+    a.cut = params->query_cut;
+    a.hf = params->heap_factor;
+    a.sort_cap = index->dev->sort_cap;
+    a.nq = (uint32_t)nq;
+    a.window = cfg.window;
+    a.queue = ws->queue;
+    a.out_ids = out_ids;
+    a.out_scores = out_scores;
+    a.prefix = stats ? stats->prefix : nullptr;
+    a.prefix_stride = stats ? stats->prefix_stride : 0;
+    a.counters = stats ? stats->counters : nullptr;
+    const uint32_t nt = cfg.threads;
+    size_t smem = seismic_dev::search_smem_bytes(nt, index->h.dim, index->dev->sort_cap, params->k);
+    int per_cu = seismic_dev::search_blocks_per_cu(nt, smem);
+    if (per_cu < 1) return fail(SEISMIC_EHIP, "search: kernel does not fit on a CU (%zu bytes of LDS)", smem);
+    if (cfg.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)cfg.blocks_per_cu);
+    uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ws->n_cu, nq);
+    HIP_TRY(seismic_dev::launch_search(a, nt, grid, smem, st));
     return SEISMIC_OK;
 }
 
@@ -179,7 +227,8 @@ int seismic_workspace_create(const seismic_index* index, uint32_t max_queries, u
     ws->device = index->dev->device;
     ws->max_queries = max_queries;
     ws->max_k = max_k;
-    int rc = check_config(ws, &ws->cfg);
+    for (auto& c : ws->cfg) c = seismic_launch_config{256, 0, 8, 0};
+    int rc = check_config(ws, &ws->cfg[0]);
     if (rc) { delete ws; return rc; }
     DeviceGuard g(ws->device);
     hipDeviceProp_t prop;
@@ -209,13 +258,13 @@ int seismic_workspace_set_config(seismic_workspace* ws, const seismic_launch_con
     if (!ws || !cfg) return fail(SEISMIC_EINVAL, "config: null argument");
     int rc = check_config(ws, cfg);
     if (rc) return rc;
-    ws->cfg = *cfg;
+    for (auto& c : ws->cfg) c = *cfg;
     return SEISMIC_OK;
 }
 
-int seismic_workspace_get_config(const seismic_workspace* ws, seismic_launch_config* cfg) {
+int seismic_workspace_get_config(const seismic_workspace* ws, uint32_t n_queries, seismic_launch_config* cfg) {
     if (!ws || !cfg) return fail(SEISMIC_EINVAL, "config: null argument");
-    *cfg = ws->cfg;
+    *cfg = ws->cfg[bucket_of(n_queries)];
     return SEISMIC_OK;
 }
 
@@ -224,14 +273,8 @@ int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, cons
                          const seismic_stats* stats, void* stream) {
     if (!index || !ws || !queries || !params || !out_ids || !out_scores)
         return fail(SEISMIC_EINVAL, "search: null argument");
-    if (!index->dev) return fail(SEISMIC_ESTATE, "search: index is not on a device");
-    if (ws->index != index) return fail(SEISMIC_EINVAL, "search: workspace belongs to another index");
-    if (params->k < 1 || params->k > ws->max_k) return fail(SEISMIC_EINVAL, "search: k = %u outside [1, %u]", params->k, ws->max_k);
-    if (!(params->heap_factor > 0.0f)) return fail(SEISMIC_EINVAL, "search: heap_factor must be > 0");
-    if (params->flags != 0) return fail(SEISMIC_EINVAL, "search: unknown flags");
-    if (queries->dim != index->h.dim) return fail(SEISMIC_EINVAL, "search: query dim %u != index dim %u", queries->dim, index->h.dim);
-    if (queries->n_rows > ws->max_queries)
-        return fail(SEISMIC_EINVAL, "search: %llu queries exceed the workspace (%u)", (unsigned long long)queries->n_rows, ws->max_queries);
+    int rc = check_params(index, ws, queries, params);
+    if (rc) return rc;
     if (stats && stats->prefix && stats->prefix_stride < 1) return fail(SEISMIC_EINVAL, "search: prefix_stride must be >= 1");
     DeviceGuard g(ws->device);
     if (!g.ok()) return fail(SEISMIC_EHIP, "search: cannot select device");
@@ -239,7 +282,7 @@ int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, cons
     const uint64_t* q_ptr = queries->row_ptr;
     const uint32_t* q_words = queries->words;
     if (!queries->on_device) {
-        int rc = validate_csr_host(queries, SEISMIC_MAX_QUERY_NNZ, "search: queries");
+        rc = validate_csr_host(queries, SEISMIC_MAX_QUERY_NNZ, "search: queries");
         if (rc) return rc;
         rc = grow((void**)&ws->q_ptr, ws->q_rows_cap, queries->n_rows + 1, sizeof(uint64_t));
         if (!rc) rc = grow((void**)&ws->q_words, ws->q_words_cap, std::max<uint64_t>(queries->nnz, 1), sizeof(uint32_t));
@@ -250,30 +293,81 @@ int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, cons
         q_ptr = ws->q_ptr;
         q_words = ws->q_words;
     }
-    seismic_dev::SearchArgs a{};
-    a.ix = index->dev->view;
-    a.q_ptr = q_ptr;
-    a.q_words = q_words;
-    a.q_nnz = queries->nnz;
-    a.k = params->k;
-    a.cut = params->query_cut;
-    a.hf = params->heap_factor;
-    a.sort_cap = index->dev->sort_cap;
-    a.nq = (uint32_t)queries->n_rows;
-    a.window = ws->cfg.window;
-    a.queue = ws->queue;
-    a.out_ids = out_ids;
-    a.out_scores = out_scores;
-    a.prefix = stats ? stats->prefix : nullptr;
-    a.prefix_stride = stats ? stats->prefix_stride : 0;
-    a.counters = stats ? stats->counters : nullptr;
-    const uint32_t nt = ws->cfg.threads;
-    size_t smem = seismic_dev::search_smem_bytes(nt, index->h.dim, index->dev->sort_cap, params->k);
-    int per_cu = seismic_dev::search_blocks_per_cu(nt, smem);
-    if (per_cu < 1) return fail(SEISMIC_EHIP, "search: kernel does not fit on a CU (%zu bytes of LDS)", smem);
-    if (ws->cfg.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)ws->cfg.blocks_per_cu);
-    uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ws->n_cu, queries->n_rows);
-    HIP_TRY(seismic_dev::launch_search(a, nt, grid, smem, st));
+    return launch_batch(index, ws, q_ptr, q_words, queries->n_rows, queries->nnz, params, out_ids, out_scores, stats,
+                        ws->cfg[bucket_of(queries->n_rows)], st);
+}
+
+int seismic_autotune(const seismic_index* index, seismic_workspace* ws, const seismic_csr* queries,
+                     const seismic_search_params* params, uint32_t* out_ids, float* out_scores, uint32_t reps,
+                     seismic_tune_result* results, uint32_t max_results, uint32_t* n_results, void* stream) {
+    if (!index || !ws || !queries || !params || !out_ids || !out_scores)
+        return fail(SEISMIC_EINVAL, "autotune: null argument");
+    if (!queries->on_device) return fail(SEISMIC_EINVAL, "autotune: queries must be device resident");
+    int rc = check_params(index, ws, queries, params);
+    if (rc) return rc;
+    if (n_results) *n_results = 0;
+    if (queries->n_rows == 0) return SEISMIC_OK;
+    if (reps < 1) reps = 1;
+    DeviceGuard g(ws->device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "autotune: cannot select device");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n_out = (size_t)queries->n_rows * params->k;
+    std::vector<uint32_t> ref_ids(n_out), ids(n_out);
+    std::vector<float> ref_sc(n_out), sc(n_out);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = INFINITY;
+    seismic_launch_config best_cfg = ws->cfg[bucket_of(queries->n_rows)];
+    uint32_t count = 0;
+    bool have_ref = false;
+    int err = SEISMIC_OK;
+    for (uint32_t nt : {256u, 512u}) {
+        size_t smem = seismic_dev::search_smem_bytes(nt, index->h.dim, index->dev->sort_cap, params->k);
+        if (smem > index->dev->smem_limit) continue;
+        const int max_pc = seismic_dev::search_blocks_per_cu(nt, smem);
+        for (int pc = 1; pc <= max_pc && !err; ++pc) {
+            for (uint32_t w : {1u, 2u, 4u, 8u, 16u}) {
+                seismic_launch_config c{nt, (uint32_t)pc, w, 0};
+                // warm-up run, then compare its results with the first shape's
+                err = launch_batch(index, ws, queries->row_ptr, queries->words, queries->n_rows, queries->nnz, params,
+                                   out_ids, out_scores, nullptr, c, st);
+                if (err) break;
+                if (hipMemcpyAsync(have_ref ? ids.data() : ref_ids.data(), out_ids, n_out * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipMemcpyAsync(have_ref ? sc.data() : ref_sc.data(), out_scores, n_out * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess) {
+                    err = fail(SEISMIC_EHIP, "autotune: copy of results failed");
+                    break;
+                }
+                if (have_ref && (std::memcmp(ids.data(), ref_ids.data(), n_out * 4) != 0 ||
+                                 std::memcmp(sc.data(), ref_sc.data(), n_out * 4) != 0)) {
+                    err = fail(SEISMIC_ESTATE, "autotune: results differ between launch shapes (threads %u, per CU %d, window %u)", nt, pc, w);
+                    break;
+                }
+                have_ref = true;
+                if (hipEventRecord(e0, st) != hipSuccess) { err = fail(SEISMIC_EHIP, "autotune: event record failed"); break; }
+                for (uint32_t r = 0; r < reps && !err; ++r)
+                    err = launch_batch(index, ws, queries->row_ptr, queries->words, queries->n_rows, queries->nnz, params,
+                                       out_ids, out_scores, nullptr, c, st);
+                if (err) break;
+                float ms = 0.0f;
+                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    err = fail(SEISMIC_EHIP, "autotune: event timing failed");
+                    break;
+                }
+                ms /= (float)reps;
+                if (results && count < max_results) results[count] = seismic_tune_result{c, ms, 0};
+                ++count;
+                if (ms < best) { best = ms; best_cfg = c; }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err) return err;
+    ws->cfg[bucket_of(queries->n_rows)] = best_cfg;
+    if (n_results) *n_results = std::min(count, max_results);
     return SEISMIC_OK;
 }
 

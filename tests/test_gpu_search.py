@@ -154,3 +154,29 @@ def test_no_pruning_full_lists_equals_exact():
     e_ids, e_sc = oracle.exact_topk(docs, qs, 10)
     assert np.array_equal(as_u32(ids), e_ids)
     assert np.array_equal(sc.cpu().numpy(), e_sc)
+
+
+def test_autotune_keeps_results_and_picks_a_shape(cfg1):
+    """The autotuner times every launch shape, checks they agree, and
+    stores the fastest one for the batch's size bucket."""
+    import torch
+    docs, qs, ix, ref_ix = cfg1
+    _log("[autotune]")
+    sub = qs.subset(range(300))
+    q = to_device_csr(sub)
+    ws = binding.seismic_workspace_create(ix.handle, 300, 10)
+    ids = torch.empty((300, 10), dtype=torch.int32, device="cuda")
+    sc = torch.empty((300, 10), dtype=torch.float32, device="cuda")
+    res = binding.seismic_autotune(ix.handle, ws, q, 10, 10, 0.8, ids, sc, reps=1)
+    assert len(res) >= 10
+    best = min(res, key=lambda r: r[1])[0]
+    assert binding.seismic_workspace_get_config(ws, 300) == best
+    ref = ref_ix.pruned_search(sub, 10, 10, 0.8, c_cap=10)
+    assert np.array_equal(as_u32(ids), ref["ids"]) and np.array_equal(sc.cpu().numpy(), ref["scores"])
+    binding.seismic_search_batch(ix.handle, ws, q, 10, 10, 0.8, ids, sc)
+    assert np.array_equal(as_u32(ids), ref["ids"])
+    with pytest.raises(SeismicError):
+        binding.seismic_workspace_set_config(ws, threads=128)
+    with pytest.raises(SeismicError):
+        binding.seismic_workspace_set_config(ws, window=0)
+    binding.seismic_workspace_free(ws)
