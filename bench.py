@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget (0 = skip)")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--profile-copy", action="store_true", help="also run a plain copy for counter calibration")
+    ap.add_argument("--index-cache", default=None, help="load the index from this file if present, else build and save")
+    ap.add_argument("--plain-rows", action="store_true", help="search the forward rows in place (no block-major copies)")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -95,12 +98,33 @@ def main():
     qs = synth.queries(W["n_queries"], seed=0, law=W["qlaw"])
     log(f"[bench] generated {docs.nnz} doc nonzeros, {qs.nnz} query nonzeros ({time.time() - t0:.1f} s)")
     t1 = time.time()
-    ix = Index.build(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, verbose=True)
-    build_s = time.time() - t1
+    cache = args.index_cache
+    if cache and os.path.exists(cache):
+        ix = Index.load(cache)
+        build_s = None
+        log(f"[bench] index loaded from {cache} in {time.time() - t1:.1f} s")
+    else:
+        ix = Index.build(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, verbose=True)
+        build_s = time.time() - t1
+        log(f"[bench] index built in {build_s:.1f} s")
+        if cache:
+            ix.save(cache)
+            log(f"[bench] index saved to {cache}")
     info = ix.info()
-    log(f"[bench] index built in {build_s:.1f} s: {info}")
-    ix.upload(0)
-    log("[bench] index resident in HBM")
+    log(f"[bench] index: {info}")
+    t1 = time.time()
+    layout = "block_rows"
+    try:
+        ix.upload(0, block_rows=not args.plain_rows)
+        layout = "rows" if args.plain_rows else "block_rows"
+    except Exception as e:  # not enough HBM for the block-major copies
+        log(f"[bench] block-major rows unavailable ({e}); plain rows")
+        ix.close()
+        ix = Index.load(cache) if cache and os.path.exists(cache) else \
+            Index.build(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads)
+        ix.upload(0)
+        layout = "rows"
+    log(f"[bench] index resident in HBM ({layout}, {time.time() - t1:.1f} s)")
 
     q_rp = torch.from_numpy(qs.row_ptr.astype(np.int64)).to(dev)
     q_w = torch.from_numpy(qs.words.view(np.int32)).to(dev)
@@ -176,6 +200,15 @@ def main():
     cnt = counters.cpu().numpy()
     bytes_per_launch = float(alg_bytes(cnt, q_nnz, k).sum())
 
+    # launch shape for this batch: the library's autotuner times every shape
+    tuned = None
+    if not args.no_autotune:
+        tt = time.time()
+        res = binding.seismic_autotune(ix.handle, ws, qcsr, k, cut, chosen, out_ids, out_sc, reps=2, stream=stream)
+        tuned = binding.seismic_workspace_get_config(ws, nq)
+        log(f"[bench] autotuned over {len(res)} shapes in {time.time() - tt:.1f} s: {tuned} "
+            f"({min(r[1] for r in res):.3f} ms; worst {max(r[1] for r in res):.3f} ms)")
+
     # timed steps
     for _ in range(args.warmup):
         run(chosen, False)
@@ -247,7 +280,8 @@ def main():
                                f"lambda {W['lam']}, beta {W['beta']}, gamma {W['gamma']}, query_cut {cut}, "
                                f"k {k}, heap_factor {chosen}",
                    "recall_at_10": point["recall"], "recall_target": args.recall,
-                   "index_build_s": round(build_s, 1), "exact_topk_s": round(exact_s, 2),
+                   "index_build_s": None if build_s is None else round(build_s, 1),
+                   "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
                    "sweep": sweep},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,

@@ -133,12 +133,18 @@ int seismic_index_load(const char* path, seismic_index** out);
 
 /* out[0..7] = dim, n_docs, nnz, n_blocks, n_postings, n_summary entries,
    lambda, beta; out[8] = largest number of blocks in one list; out[9] = 1
-   when the index is resident on a device. */
+   when the index is resident on a device (2 with block-major rows). */
 int seismic_index_info(const seismic_index* index, uint64_t out[10]);
 
 /* Copy the index to HBM of HIP device `device` (synchronous).  Required
-   before search.  ENOMEM if it does not fit, EHIP on runtime errors. */
-int seismic_index_upload(seismic_index* index, int device);
+   before search.  ENOMEM if it does not fit, EHIP on runtime errors.
+   flags: SEISMIC_UPLOAD_BLOCK_ROWS additionally stores, block after block,
+   a copy of the forward rows of every block's documents (each row padded
+   to 16 bytes with zero words), so that evaluating a block reads one
+   contiguous run instead of scattered rows; it costs about 4 bytes per
+   nonzero per posting of device memory and never changes results. */
+#define SEISMIC_UPLOAD_BLOCK_ROWS 1u
+int seismic_index_upload(seismic_index* index, int device, uint32_t flags);
 
 /* Release host and device memory of the index. */
 void seismic_index_free(seismic_index* index);

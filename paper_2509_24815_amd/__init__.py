@@ -38,8 +38,8 @@ class Index:
     def info(self) -> dict:
         return binding.seismic_index_info(self.handle)
 
-    def upload(self, device: int = 0):
-        binding.seismic_index_upload(self.handle, device)
+    def upload(self, device: int = 0, block_rows: bool = False):
+        binding.seismic_index_upload(self.handle, device, block_rows)
 
     def workspace(self, max_queries: int, max_k: int) -> int:
         key = (max_queries, max_k)

@@ -78,7 +78,7 @@ def load():
         "seismic_index_save": ([vp, ctypes.c_char_p], i32),
         "seismic_index_load": ([ctypes.c_char_p, P(vp)], i32),
         "seismic_index_info": ([vp, vp], i32),
-        "seismic_index_upload": ([vp, i32], i32),
+        "seismic_index_upload": ([vp, i32, u32], i32),
         "seismic_index_free": ([vp], None),
         "seismic_workspace_create": ([vp, u32, u32, P(vp)], i32),
         "seismic_workspace_free": ([vp], None),
@@ -169,8 +169,8 @@ def seismic_index_info(handle) -> dict:
     return {k: int(v) for k, v in zip(keys, out)}
 
 
-def seismic_index_upload(handle, device: int = 0):
-    _check(load().seismic_index_upload(handle, device))
+def seismic_index_upload(handle, device: int = 0, block_rows: bool = False):
+    _check(load().seismic_index_upload(handle, device, 1 if block_rows else 0))
 
 
 def seismic_index_free(handle):

@@ -34,6 +34,8 @@ struct DeviceIndex {
     size_t xq_rows_cap = 0, xq_words_cap = 0;
 };
 
+int device_index_layout(const DeviceIndex* d) { return !d ? 0 : d->view.brow ? 2 : 1; }
+
 void device_index_free(DeviceIndex* d) {
     if (!d) return;
     int prev = 0;
@@ -172,12 +174,64 @@ int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64
     return SEISMIC_OK;
 }
 
+// Copy the row of posting p (document postings[p]) to 16-byte groups
+// [prow[p], prow[p+1]) of brow, zero-padded.  One wave per posting.
+__global__ __launch_bounds__(256) void k_build_block_rows(const uint64_t* row_ptr, const uint32_t* words,
+                                                          const uint32_t* postings, const uint64_t* prow,
+                                                          uint64_t n_postings, uint32_t* brow) {
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t n_waves = (uint64_t)gridDim.x * blockDim.x / 64;
+    for (uint64_t p = wave; p < n_postings; p += n_waves) {
+        const uint32_t d = postings[p];
+        const uint64_t rs = row_ptr[d], len = row_ptr[d + 1] - rs;
+        const uint64_t dst = prow[p] * 4, n = (prow[p + 1] - prow[p]) * 4;
+        for (uint64_t i = lane; i < n; i += 64) brow[dst + i] = i < len ? words[rs + i] : 0u;
+    }
+}
+
+// Block-major copies of the rows: posting order is block order, so the
+// rows of a block are one contiguous run.
+int build_block_rows(DeviceIndex* d, const HostIndex& h) {
+    const uint64_t np = h.postings.size();
+    std::vector<uint64_t> prow(np + 1);
+    std::vector<uint32_t> pnnz(np);
+    uint64_t run = 0;
+    for (uint64_t p = 0; p < np; ++p) {
+        const uint32_t doc = h.postings[p];
+        const uint64_t len = h.row_ptr[doc + 1] - h.row_ptr[doc];
+        prow[p] = run;
+        pnnz[p] = (uint32_t)len;
+        run += (len + 3) / 4;
+    }
+    prow[np] = run;
+    DevIdx& v = d->view;
+    int rc = upload_vec(d, prow, v.prow);
+    if (!rc) rc = upload_vec(d, pnnz, v.pnnz);
+    if (rc) return rc;
+    void* brow = nullptr;
+    const size_t bytes = (size_t)(run + 2) * 16;  // +2 groups: vector loads past the end stay inside
+    hipError_t e = hipMalloc(&brow, bytes);
+    if (e != hipSuccess) return fail(SEISMIC_ENOMEM, "upload: block-major rows need %zu bytes: %s", bytes, hipGetErrorString(e));
+    d->allocs.push_back(brow);
+    HIP_TRY(hipMemset((uint8_t*)brow + run * 16, 0, 32));
+    if (np) {
+        hipLaunchKernelGGL(k_build_block_rows, dim3(8192), dim3(256), 0, nullptr, v.row_ptr, v.words, v.postings, v.prow,
+                           np, (uint32_t*)brow);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipDeviceSynchronize());
+    }
+    v.brow = (const uint32_t*)brow;
+    return SEISMIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int seismic_index_upload(seismic_index* index, int device) {
+int seismic_index_upload(seismic_index* index, int device, uint32_t flags) {
     if (!index) return fail(SEISMIC_EINVAL, "upload: null index");
+    if (flags & ~SEISMIC_UPLOAD_BLOCK_ROWS) return fail(SEISMIC_EINVAL, "upload: unknown flags");
     std::lock_guard<std::mutex> lk(index->mu);
     if (index->dev) return fail(SEISMIC_ESTATE, "upload: index already on device %d", index->dev->device);
     int ndev = 0;
@@ -209,6 +263,7 @@ int seismic_index_upload(seismic_index* index, int device) {
     if (!rc) rc = upload_vec(d, h.postings, v.postings);
     if (!rc) rc = upload_vec(d, h.sum_term, v.sum_term, 16);
     if (!rc) rc = upload_vec(d, h.sum_code, v.sum_code, 16);
+    if (!rc && (flags & SEISMIC_UPLOAD_BLOCK_ROWS)) rc = build_block_rows(d, h);
     if (rc) { device_index_free(d); return rc; }
     v.dim = h.dim;
     v.n_docs = (uint32_t)h.n_docs;

@@ -20,6 +20,11 @@ struct DevIdx {
     const uint32_t* postings;
     const uint16_t* sum_term;  // padded to a multiple of 8 entries (+8)
     const uint8_t* sum_code;   // padded likewise
+    // block-major rows (optional): posting p's row occupies 16-byte groups
+    // [prow[p], prow[p+1]) of brow, zero-padded; pnnz[p] = its nonzeros
+    const uint64_t* prow;
+    const uint32_t* pnnz;
+    const uint32_t* brow;
     uint32_t dim;
     uint32_t n_docs;
 };

@@ -9,7 +9,8 @@
 
 #include "internal.h"
 
-void device_index_free(DeviceIndex* d);  // device.hip
+void device_index_free(DeviceIndex* d);          // device.hip
+int device_index_layout(const DeviceIndex* d);  // 0 none, 1 resident, 2 with block-major rows
 
 namespace seismic {
 
@@ -657,7 +658,7 @@ int seismic_index_info(const seismic_index* index, uint64_t out[10]) {
     out[0] = h.dim; out[1] = h.n_docs; out[2] = h.nnz(); out[3] = h.n_blocks();
     out[4] = h.postings.size(); out[5] = h.sum_term.size(); out[6] = h.lambda; out[7] = h.beta;
     out[8] = h.max_blocks_per_list();
-    out[9] = index->dev ? 1 : 0;
+    out[9] = device_index_layout(index->dev);
     return SEISMIC_OK;
 }
 

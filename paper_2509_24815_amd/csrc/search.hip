@@ -210,23 +210,33 @@ __device__ __forceinline__ void summary_group(const SearchLds<NT>& L, const Look
 // (words outside the row are replaced by 0, which adds exactly 0) with
 // kUnroll loads per document in flight, and reduce with shuffles.  On return
 // cacc[t] is the exact score of document t (fp64) and clen[t] its number of
-// nonzeros.  Every thread calls it; it ends with a barrier.
-template <int NT, typename Look>
-__device__ inline void gather_and_score(const DevIdx& ix, const SearchLds<NT>& L, const Look& look, uint32_t tot,
-                                        uint32_t nwb, uint32_t big_off) {
+// nonzeros.  Every thread calls it; it ends with a barrier.  BR: the index
+// holds block-major rows (16-byte aligned, zero-padded: no masking needed).
+template <int NT, typename Look, bool BR>
+__device__ inline void gather_and_score_t(const DevIdx& ix, const SearchLds<NT>& L, const Look& look, uint32_t tot,
+                                          uint32_t nwb, uint32_t big_off) {
     const int tid = threadIdx.x;
     if ((uint32_t)tid < tot) {
         uint32_t s = 0;
         while (s + 1 < nwb && L.wst[s + 1] <= (uint32_t)tid) ++s;
         const uint32_t p = L.wp0[s] + big_off + ((uint32_t)tid - L.wst[s]);
         const uint32_t d = ix.postings[p];
-        const uint64_t rs = ix.row_ptr[d], re = ix.row_ptr[d + 1];
+        uint64_t rs;
+        uint32_t len;
+        if (BR) {  // block-major copy: contiguous with its neighbours, 16-byte aligned
+            rs = ix.prow[p] << 2;
+            len = ix.pnnz[p];
+        } else {
+            rs = ix.row_ptr[d];
+            len = (uint32_t)(ix.row_ptr[d + 1] - rs);
+        }
         L.cdoc[tid] = d;
         L.crs[tid] = rs;
-        L.clen[tid] = (uint32_t)(re - rs);
+        L.clen[tid] = len;
         L.cslot[tid] = (uint8_t)s;
     }
     __syncthreads();
+    const uint32_t* src = BR ? ix.brow : ix.words;
     constexpr uint32_t G = kLanesPerDoc, NG = NT / kLanesPerDoc;
     const uint32_t grp = (uint32_t)tid / G, gl = (uint32_t)tid % G;
     for (uint32_t base = grp; base < tot; base += 2 * NG) {
@@ -248,7 +258,7 @@ __device__ inline void gather_and_score(const DevIdx& ix, const SearchLds<NT>& L
             for (uint32_t h = 0; h < 2; ++h)
 #pragma unroll
                 for (uint32_t u = 0; u < kUnroll; ++u)
-                    w[h][u] = (k + u * G < ng[h]) ? *(const uint4*)(ix.words + ((g0[h] + k + u * G) << 2))
+                    w[h][u] = (k + u * G < ng[h]) ? *(const uint4*)(src + ((g0[h] + k + u * G) << 2))
                                                  : make_uint4(0, 0, 0, 0);
 #pragma unroll
             for (uint32_t h = 0; h < 2; ++h)
@@ -260,7 +270,7 @@ __device__ inline void gather_and_score(const DevIdx& ix, const SearchLds<NT>& L
 #pragma unroll
                     for (uint32_t e = 0; e < 4; ++e) {
                         const int32_t at = rel + (int32_t)e;
-                        const uint32_t x = (at >= 0 && at < (int32_t)len[h]) ? ww[e] : 0u;
+                        const uint32_t x = (BR || (at >= 0 && at < (int32_t)len[h])) ? ww[e] : 0u;
                         acc[h] = fma(look(x & 0xFFFFu), (double)half_bits_to_float(x >> 16), acc[h]);
                     }
                 }
@@ -273,6 +283,15 @@ __device__ inline void gather_and_score(const DevIdx& ix, const SearchLds<NT>& L
         }
     }
     __syncthreads();
+}
+
+template <int NT, typename Look>
+__device__ inline void gather_and_score(const DevIdx& ix, const SearchLds<NT>& L, const Look& look, uint32_t tot,
+                                        uint32_t nwb, uint32_t big_off) {
+    if (ix.brow)
+        gather_and_score_t<NT, Look, true>(ix, L, look, tot, nwb, big_off);
+    else
+        gather_and_score_t<NT, Look, false>(ix, L, look, tot, nwb, big_off);
 }
 
 // Fold the gathered documents of window slot `slot` (all of them when

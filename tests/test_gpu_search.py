@@ -20,17 +20,19 @@ def _log(msg):
     print(msg, flush=True)
 
 
-@pytest.fixture(scope="module")
-def cfg1():
-    """100k documents, lambda 1000, beta 50, gamma 0.4; 1000 Poisson(43) queries."""
+@pytest.fixture(scope="module", params=[False, True], ids=["rows", "block_rows"])
+def cfg1(request):
+    """100k documents, lambda 1000, beta 50, gamma 0.4; 1000 Poisson(43)
+    queries.  Run with the plain forward rows and with block-major copies."""
     import torch
-    _log("[cfg1] generating 100k docs / 1000 queries, building index")
+    _log(f"[cfg1] generating 100k docs / 1000 queries, building index (block_rows={request.param})")
     docs = synth.docs(100_000, seed=0)
     qs = synth.queries(1000, seed=0)
     ix = Index.build(docs, lam=1000, beta=50, gamma=0.4, seed=0)
     ref_ix = oracle.Index(ix.serialize())
     torch.cuda.set_device(0)
-    ix.upload(0)
+    ix.upload(0, block_rows=request.param)
+    assert ix.info()["on_device"] == (2 if request.param else 1)
     return docs, qs, ix, ref_ix
 
 
