@@ -39,6 +39,43 @@ WORKLOADS = {
 
 PEAK_HBM_GBS = 8000.0
 
+# Sources of the search kernel: a traffic figure taken from rocprofv3 counters
+# is reported only while these files are unchanged since the counters were read.
+KERNEL_SOURCES = ("paper_2509_24815_amd/csrc/search.hip", "paper_2509_24815_amd/csrc/device_common.h",
+                  "paper_2509_24815_amd/csrc/search_kernels.h")
+
+
+def kernel_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, hf: float, k: int):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary
+    of this workload and operating point, or None when there is none or the
+    kernel has changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"k_search_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith((" ", "|", "#")):
+                key, val = line.split(":", 1)
+                kv[key.strip()] = val.strip()
+    try:
+        if kv.get("source_sha256") != kernel_sha():
+            return None
+        if kv.get("workload") != f"{workload} heap_factor {hf} k {k}":
+            return None
+        return float(kv["traffic_bytes_per_launch"].split()[0])
+    except (KeyError, ValueError):
+        return None
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -263,6 +300,7 @@ def main():
         log(f"[bench] CPU baseline {cpu}")
         del ref, buf
 
+    traffic = measured_traffic(args.workload, chosen, k)
     out = {
         "metric": "QPS at Recall@10>=0.95 (1 GPU, 8.8M docs); p50/p99 query latency",
         "value": round(qps, 1),
@@ -284,7 +322,9 @@ def main():
                    "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
                    "sweep": sweep},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "traffic_frac": None if traffic is None else round(traffic / (ms_per_step / 1e3) / 1e9
+                                                                           / PEAK_HBM_GBS, 4),
                      "alg_bytes_per_launch": bytes_per_launch},
         "cpu_baseline": cpu,
     }
