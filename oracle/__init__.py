@@ -23,6 +23,8 @@ _lib = None
 EXACT_SUMMARIES = 1  # r_j = <q, phi(B_j)> with full max vectors, no sketch and no quantization
 CONTINUE = 2         # literal "continue" on a skipped block instead of stopping the list
 
+PROBE_WORDS = 512   # learned block probe: W1[64][5], b1[64], w2[64], b2, zero padding (bf16)
+
 COUNTER_NAMES = ("summary_entries", "blocks_in_lists", "blocks_evaluated", "docs_evaluated",
                  "nnz_evaluated", "prune_tests", "near_tie_tests", "cut_len")
 
@@ -59,8 +61,13 @@ def _load():
     lib.or_value_range.restype = i32
     lib.or_exact_topk.argtypes = [vp, vp, u64, vp, vp, u64, ctypes.c_uint32, i32, vp, vp, i32]
     lib.or_exact_topk.restype = i32
-    lib.or_pruned_search.argtypes = [vp, vp, vp, u64, i32, i32, f32, ctypes.c_uint32, i32, i32, vp, vp, vp, vp]
+    lib.or_pruned_search.argtypes = [vp, vp, vp, u64, i32, i32, f32, ctypes.c_uint32, i32, i32, vp, vp, vp, vp,
+                                     vp, f64, vp]
     lib.or_pruned_search.restype = i32
+    lib.or_probe_eval.argtypes = [vp, vp, vp, vp, vp, vp, u64, vp, vp]
+    lib.or_probe_eval.restype = i32
+    lib.or_probe_quantize.argtypes = [vp, u64, i32, vp]
+    lib.or_probe_quantize.restype = None
     lib.or_check_index.argtypes = [vp, i32, i32, ctypes.c_char_p, i32]
     lib.or_check_index.restype = i32
     lib.or_column_keep.argtypes = [vp, vp, u64, u64, vp]
@@ -163,9 +170,11 @@ class Index:
         return "" if rc == 0 else (msg.value.decode() or "check failed")
 
     def pruned_search(self, queries, k: int, cut: int, heap_factor: float, flags: int = 0,
-                      nthreads: int = 0, c_cap: int | None = None):
+                      nthreads: int = 0, c_cap: int | None = None, probe=None, tau: float = 0.0):
         """Algorithm 2 block-pruned search.  Returns a dict with ids, scores,
-        prefix (evaluated blocks per cut list) and counters."""
+        prefix (evaluated blocks per cut list), counters and hmin (smallest
+        heap score at each cut list's start, -1 when the heap is not full).
+        probe: 512 bf16 weights as uint16 (learned block probe) or None."""
         lib = _load()
         qrp, qw = _csr(queries)
         nq = len(qrp) - 1
@@ -176,11 +185,18 @@ class Index:
         sc = np.empty((nq, k), dtype=np.float32)
         pref = np.zeros((nq, c_cap), dtype=np.uint16)
         cnt = np.zeros((nq, 8), dtype=np.uint64)
+        hmin = np.zeros((nq, c_cap), dtype=np.float32)
+        pw = None
+        if probe is not None:
+            pw = np.ascontiguousarray(probe, dtype=np.uint16)
+            if pw.size != PROBE_WORDS:
+                raise ValueError(f"probe must hold {PROBE_WORDS} bf16 words")
         rc = lib.or_pruned_search(self._h, _p(qrp), _p(qw), nq, k, cut, float(heap_factor), flags,
-                                  nthreads or os.cpu_count() or 1, c_cap, _p(ids), _p(sc), _p(pref), _p(cnt))
+                                  nthreads or os.cpu_count() or 1, c_cap, _p(ids), _p(sc), _p(pref), _p(cnt),
+                                  None if pw is None else _p(pw), float(tau), _p(hmin))
         if rc != 0:
             raise ValueError(f"or_pruned_search failed ({rc})")
-        return {"ids": ids, "scores": sc, "prefix": pref, "counters": cnt}
+        return {"ids": ids, "scores": sc, "prefix": pref, "counters": cnt, "hmin": hmin}
 
 
 def column_keep(ids, halfs, lam: int):
@@ -206,3 +222,29 @@ def quantize(halfs):
     d = ctypes.c_float(0.0)
     _load().or_quantize(_p(h), len(h), ctypes.byref(m), ctypes.byref(d), _p(codes))
     return m.value, d.value, codes[:len(h)]
+
+
+def probe_eval(probe, r, h0, n_docs, n_q, ci):
+    """Quantized features [n, 5] and exact logits [n] of the learned block
+    probe for explicit (r, h0, n_docs, n_q, ci) rows."""
+    pw = np.ascontiguousarray(probe, dtype=np.uint16)
+    assert pw.size == PROBE_WORDS
+    r = np.ascontiguousarray(r, dtype=np.float32)
+    n = r.size
+    h0 = np.ascontiguousarray(np.broadcast_to(h0, n), dtype=np.float32)
+    nd = np.ascontiguousarray(np.broadcast_to(n_docs, n), dtype=np.uint32)
+    nqa = np.ascontiguousarray(np.broadcast_to(n_q, n), dtype=np.int32)
+    cia = np.ascontiguousarray(np.broadcast_to(ci, n), dtype=np.int32)
+    feat = np.zeros((n, 5), dtype=np.float64)
+    z = np.zeros(n, dtype=np.float64)
+    _load().or_probe_eval(_p(pw), _p(r), _p(h0), _p(nd), _p(nqa), _p(cia), n, _p(feat), _p(z))
+    return feat, z
+
+
+def probe_quantize(x, mode: int):
+    """mode 0: feature quantizer, 1: hidden quantizer, 2: weight sanitizer
+    (x = bf16 bit patterns)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    _load().or_probe_quantize(_p(x), x.size, int(mode), _p(out))
+    return out

@@ -287,6 +287,115 @@ int or_exact_topk(const uint64_t* d_ptr, const uint32_t* d_words, uint64_t n_doc
 
 #define OR_NEAR_TIE_REL 1e-5
 
+/* ------------------------------------------------ learned block probe
+ *
+ * Not part of the paper: a 2-layer MLP (5 -> 64 -> 1, ReLU) that replaces
+ * the heap_factor test for a cut list whose traversal starts with a full
+ * heap.  Weights are 512 bf16 values: W1[64][5] (row = hidden unit), b1[64],
+ * w2[64], b2, then zero padding.  Every step is defined so that the logit is
+ * an exact number:
+ *   - a stored weight w becomes 0 when NaN or |w| < 2^-12 and +-16 when
+ *     |w| > 16;
+ *   - the features of block j of cut list ci (heap full at the list's start,
+ *     smallest heap score h0) are q(r_j / 16), q(r_j / h0), q(n_docs / 64),
+ *     q(n_q / 64), q(ci / 8), each ratio taken in fp64 (one rounding), where
+ *     q(x) is x rounded to bf16 (nearest, ties to even), then 0 below 2^-8
+ *     and 16 above 16;
+ *   - a_l = b1_l + sum_i W1[l][i] f_i and z = b2 + sum_l w2_l h_l with
+ *     h_l = 0 for a_l <= 0, else a_l rounded to bf16, 0 below 2^-8 and 256
+ *     above 256.  Every product is a multiple of 2^-34 and every sum stays
+ *     below 2^19, so both sums are exact in fp64.
+ * The list's blocks are visited by (z desc, block asc) and the list stops at
+ * the first block with z < tau; a list that starts with a non-full heap uses
+ * the heap_factor rule.  Parity unpinned by the paper (the probe is not in
+ * it): pinned by its special cases in the tests. */
+
+#define OR_PROBE_WORDS 512
+#define OR_PROBE_HIDDEN 64
+#define OR_PROBE_IN 5
+
+static double bf16_value(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* x > 0 rounded to 8 significant bits, ties to even (rint in the default
+   rounding mode). */
+static double round_bf16(double x) {
+    int e;
+    double m = frexp(x, &e); /* x = m * 2^e, m in [0.5, 1) */
+    return ldexp(rint(ldexp(m, 8)), e - 8);
+}
+
+static double probe_q(double x, double lo, double hi) {
+    if (!(x > 0.0)) return 0.0;
+    double y = round_bf16(x);
+    if (y < lo) return 0.0;
+    if (y > hi) return hi;
+    return y;
+}
+
+static double probe_weight(uint16_t b) {
+    double w = bf16_value(b);
+    if (isnan(w) || fabs(w) < 0x1p-12) return 0.0;
+    if (w > 16.0) return 16.0;
+    if (w < -16.0) return -16.0;
+    return w;
+}
+
+/* Logit of one feature vector f[5] (already quantized). */
+static double probe_logit(const double* W, const double* f) {
+    const double* W1 = W;
+    const double* b1 = W + OR_PROBE_HIDDEN * OR_PROBE_IN;
+    const double* w2 = b1 + OR_PROBE_HIDDEN;
+    double z = w2[OR_PROBE_HIDDEN];
+    for (int l = 0; l < OR_PROBE_HIDDEN; ++l) {
+        double a = b1[l];
+        for (int i = 0; i < OR_PROBE_IN; ++i) a += W1[l * OR_PROBE_IN + i] * f[i];
+        z += w2[l] * probe_q(a, 0x1p-8, 256.0);
+    }
+    return z;
+}
+
+static void probe_features(float r, double h0, uint32_t n_docs, int n_q, int ci, double* f) {
+    f[0] = probe_q((double)r / 16.0, 0x1p-8, 16.0);
+    f[1] = probe_q((double)r / h0, 0x1p-8, 16.0);
+    f[2] = probe_q((double)n_docs / 64.0, 0x1p-8, 16.0);
+    f[3] = probe_q((double)n_q / 64.0, 0x1p-8, 16.0);
+    f[4] = probe_q((double)ci / 8.0, 0x1p-8, 16.0);
+}
+
+/* Sanitized weights as fp64 (449 used values). */
+static void probe_unpack(const uint16_t* probe, double* W) {
+    for (int i = 0; i < OR_PROBE_WORDS; ++i) W[i] = probe_weight(probe[i]);
+}
+
+/* Quantized features and logits for explicit inputs: rows of
+   (r, h0, n_docs, n_q, ci). */
+int or_probe_eval(const uint16_t* probe, const float* r, const float* h0, const uint32_t* n_docs,
+                  const int32_t* n_q, const int32_t* ci, uint64_t n, double* out_feat, double* out_z) {
+    double W[OR_PROBE_WORDS];
+    probe_unpack(probe, W);
+    for (uint64_t s = 0; s < n; ++s) {
+        double* f = out_feat + s * OR_PROBE_IN;
+        probe_features(r[s], (double)h0[s], n_docs[s], n_q[s], ci[s], f);
+        out_z[s] = probe_logit(W, f);
+    }
+    return 0;
+}
+
+/* The quantizers alone, for pins: mode 0 = feature q(), 1 = hidden q(),
+   2 = stored-weight sanitizer (x holds bf16 bits as integers). */
+void or_probe_quantize(const double* x, uint64_t n, int mode, double* out) {
+    for (uint64_t i = 0; i < n; ++i) {
+        if (mode == 0) out[i] = probe_q(x[i], 0x1p-8, 16.0);
+        else if (mode == 1) out[i] = probe_q(x[i], 0x1p-8, 256.0);
+        else out[i] = probe_weight((uint16_t)x[i]);
+    }
+}
+
 typedef struct { uint32_t term; uint16_t h; double v; } qent;
 
 /* Query cut order: value desc, then term id asc. */
@@ -297,13 +406,21 @@ static int cmp_qent(const void* a, const void* b) {
     return (x->term > y->term) - (x->term < y->term);
 }
 
-typedef struct { float r; uint32_t j; } rblk;
+typedef struct { float r; uint32_t j; double z; } rblk;
 
 /* Block order: summary score desc, then block index asc. */
 static int cmp_rblk(const void* a, const void* b) {
     const rblk* x = (const rblk*)a;
     const rblk* y = (const rblk*)b;
     if (x->r != y->r) return x->r > y->r ? -1 : 1;
+    return (x->j > y->j) - (x->j < y->j);
+}
+
+/* Learned order: logit desc, then block index asc. */
+static int cmp_zblk(const void* a, const void* b) {
+    const rblk* x = (const rblk*)a;
+    const rblk* y = (const rblk*)b;
+    if (x->z != y->z) return x->z > y->z ? -1 : 1;
     return (x->j > y->j) - (x->j < y->j);
 }
 
@@ -353,11 +470,18 @@ static float summary_score_exact(const or_index* ix, const double* qd, uint64_t 
  *   2 blocks evaluated, 3 documents in evaluated blocks,
  *   4 nonzeros of those documents, 5 prune tests with a full heap,
  *   6 near-tie prune tests (|r*hf - min| <= 1e-5 * min), 7 cut length.
+ * With a probe (not NULL), a list that starts with a full heap is walked by
+ * the learned rule instead (see the probe section above); each of its blocks
+ * counts as one prune test.  out_hmin (may be NULL) receives, per cut list,
+ * the smallest heap score at the list's start (-1 when the heap is not full).
  */
 int or_pruned_search(const or_index* ix, const uint64_t* q_ptr, const uint32_t* q_words, uint64_t nq,
                      int k, int cut, float hf, uint32_t flags, int nthreads, int c_cap,
-                     uint32_t* out_ids, float* out_scores, uint16_t* out_prefix, uint64_t* out_counters) {
+                     uint32_t* out_ids, float* out_scores, uint16_t* out_prefix, uint64_t* out_counters,
+                     const uint16_t* probe, double tau, float* out_hmin) {
     if (k < 1 || cut < 0 || !(hf > 0.0f) || c_cap < 1) return -1;
+    double PW[OR_PROBE_WORDS];
+    if (probe) probe_unpack(probe, PW);
     const uint32_t dim = ix->dim;
     int bad = 0;
 #pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
@@ -376,6 +500,7 @@ int or_pruned_search(const or_index* ix, const uint64_t* q_ptr, const uint32_t* 
             uint16_t* pref = out_prefix + (size_t)qi * c_cap;
             memset(cnt, 0, 8 * sizeof(uint64_t));
             for (int c = 0; c < c_cap; ++c) pref[c] = 0;
+            if (out_hmin) for (int c = 0; c < c_cap; ++c) out_hmin[(size_t)qi * c_cap + c] = -1.0f;
             int nqe = 0;
             for (uint64_t j = q_ptr[qi]; j < q_ptr[qi + 1]; ++j) {
                 uint32_t t = w_term(q_words[j]);
@@ -395,21 +520,32 @@ int or_pruned_search(const or_index* ix, const uint64_t* q_ptr, const uint32_t* 
                 uint32_t t = qe[ci].term;
                 uint32_t b0 = ix->list_off[t], b1 = ix->list_off[t + 1];
                 uint32_t nb = b1 - b0;
+                if (hn == k && out_hmin) out_hmin[(size_t)qi * c_cap + ci] = hs[k - 1];
                 if (nb == 0) continue;
                 if (nb > rb_cap) { rb_cap = nb; rb = (rblk*)realloc(rb, sizeof(rblk) * rb_cap); }
+                const int learned = probe != NULL && hn == k;
                 for (uint32_t j = 0; j < nb; ++j) {
                     uint64_t b = (uint64_t)b0 + j;
                     rb[j].j = j;
                     if (flags & OR_EXACT_SUMMARIES) rb[j].r = summary_score_exact(ix, qd, b, phi, touched);
                     else rb[j].r = summary_score(ix, qd, b);
                     cnt[0] += ix->blk_sum_off[b + 1] - ix->blk_sum_off[b];
+                    if (learned) {
+                        double f[OR_PROBE_IN];
+                        probe_features(rb[j].r, (double)hs[k - 1], ix->blk_post_off[b + 1] - ix->blk_post_off[b],
+                                       nqe, ci, f);
+                        rb[j].z = probe_logit(PW, f);
+                    }
                 }
                 cnt[1] += nb;
-                qsort(rb, nb, sizeof(rblk), cmp_rblk);
+                qsort(rb, nb, sizeof(rblk), learned ? cmp_zblk : cmp_rblk);
+                if (learned) cnt[5] += nb;
                 uint32_t evaluated = 0;
                 for (uint32_t pos = 0; pos < nb; ++pos) {
                     uint64_t b = (uint64_t)b0 + rb[pos].j;
-                    if (hn == k) {
+                    if (learned) {
+                        if (rb[pos].z < tau) break;
+                    } else if (hn == k) {
                         double lhs = (double)rb[pos].r * (double)hf;
                         double hmin = (double)hs[k - 1];
                         cnt[5]++;
