@@ -82,26 +82,47 @@ typedef struct {
    of largest query coordinates whose lists are visited (0 = all of them),
    the fixed-size stand-in for the alpha_q-MSS of the query; heap_factor > 0:
    a block whose summary score r satisfies r * heap_factor < heap.min (with a
-   full heap) is skipped and ends its list; +INFINITY disables pruning. */
+   full heap) is skipped and ends its list; +INFINITY disables pruning.
+
+   probe (device pointer, or NULL for the heap_factor rule alone): the
+   SEISMIC_PROBE_WORDS bf16 parameters of the learned block probe, an
+   addition to the method.  A cut list whose traversal starts with a full
+   heap then evaluates exactly its blocks with probe logit >= probe_tau,
+   where the logit is a 5 -> 64 -> 1 ReLU MLP of the block's features
+   (r / 16, r / heap.min at the list's start, documents / 64, query
+   nonzeros / 64, cut rank / 8, each rounded to bf16), evaluated exactly
+   (the full definition is in the library source, probe.h).  Lists that
+   start with a non-full heap keep the heap_factor rule. */
 typedef struct {
     uint32_t k;
     uint32_t query_cut;
     float heap_factor;
     uint32_t flags; /* must be 0 */
+    const uint16_t* probe;
+    double probe_tau;
 } seismic_search_params;
+
+#define SEISMIC_PROBE_WORDS 512 /* W1[64][5] (row = hidden unit), b1[64], w2[64], b2, zero padding */
 
 /* Optional per-query statistics (device pointers; each may be NULL).
    prefix[q * prefix_stride + i] = number of blocks evaluated in the i-th
    visited list of query q (0 beyond the cut); counters[q * 8 + j]:
    0 summary entries of the visited lists, 1 blocks of the visited lists,
    2 blocks evaluated, 3 documents in evaluated blocks, 4 nonzeros of those
-   documents, 5 prune tests made with a full heap, 6 status (0 = the query
-   row was valid, else a SEISMIC_QSTATUS_* bit set), 7 visited lists. */
+   documents, 5 prune tests made with a full heap (a probe-owned list counts
+   one per block), 6 status (0 = the query row was valid, else a
+   SEISMIC_QSTATUS_* bit set), 7 visited lists.
+   list_hmin[q * prefix_stride + i] = smallest heap score when the i-th
+   visited list starts (-1 when the heap is not full, or past the cut);
+   list_term[q * prefix_stride + i] = that list's term (0xFFFFFFFF past the
+   cut).  These two are the input of seismic_probe_collect. */
 typedef struct {
     uint16_t* prefix;
     uint32_t prefix_stride;
     uint32_t reserved;
     uint64_t* counters;
+    float* list_hmin;
+    uint32_t* list_term;
 } seismic_stats;
 
 #define SEISMIC_QSTATUS_TERM_RANGE 1u /* a term id >= dim was ignored */
@@ -221,6 +242,64 @@ int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, cons
  */
 int exact_topk(const seismic_index* index, const seismic_csr* queries, uint32_t k, uint32_t* out_ids,
                float* out_scores, void* stream);
+
+/* ------------------------------------------------ learned block probe
+ * An addition to the method (not in the paper): training on the device.
+ * All buffers are caller-owned device memory; calls are asynchronous on
+ * stream. */
+
+/* Training samples from one plain search of device-resident queries: for
+ * query q and its i-th cut list (i < stride) whose traversal started with a
+ * full heap (list_term / list_hmin from seismic_stats of that search), every
+ * block j of the list gives one sample at slot s = (q * stride + i) *
+ * max_blocks + j: out_feat[s * 8 .. s * 8 + 5) = its five probe features as
+ * bf16 (the other 3 words 0) and out_label[s] = 1 if the block holds one of
+ * the query's exact top-k documents (exact_ids [n_rows * exact_k], e.g.
+ * from exact_topk), else 0.  Slots without a sample get label 255.
+ * max_blocks must be >= the largest list's block count (seismic_index_info
+ * out[8]); exact_k <= 1024.  Query rows must be valid (see Conventions). */
+int seismic_probe_collect(const seismic_index* index, const seismic_csr* queries, const uint32_t* list_term,
+                          const float* list_hmin, uint32_t stride, const uint32_t* exact_ids, uint32_t exact_k,
+                          uint32_t max_blocks, uint16_t* out_feat, uint8_t* out_label, void* stream);
+
+typedef struct seismic_probe_trainer seismic_probe_trainer; /* device scratch for up to max_batch samples */
+int seismic_probe_trainer_create(int device, uint32_t max_batch, seismic_probe_trainer** out);
+void seismic_probe_trainer_free(seismic_probe_trainer* trainer);
+
+/* Sample weights of the cross-entropy: pos_weight for label 1;
+   neg_weight + neg_weight_per_doc * feature 2 (documents / 64) for label 0,
+   so that a negative costs in proportion to the documents it would make the
+   search score. */
+typedef struct {
+    float pos_weight;
+    float neg_weight;
+    float neg_weight_per_doc;
+    uint32_t reserved;
+} seismic_probe_loss;
+
+/* Forward and backward pass over n samples (order[i] = sample index, NULL =
+ * 0..n-1; samples with label 255 are skipped).  loss = sum of
+ * w_s * (softplus(z_s) - y_s * z_s) with z_s the exact inference logit under
+ * `weights` (SEISMIC_PROBE_WORDS bf16).  grad_out [512] fp32 = gradient sum
+ * (the hidden rounding passed straight through where the pre-activation is
+ * positive), accumulated in fp32 in a fixed order (deterministic);
+ * stats_out [4] = loss sum, sample count, positives, weight sum.
+ * n <= the trainer's max_batch. */
+int seismic_probe_grad(seismic_probe_trainer* trainer, const uint16_t* feat, const uint8_t* label,
+                       const uint32_t* order, uint32_t n, const seismic_probe_loss* loss, const uint16_t* weights,
+                       float* grad_out, float* stats_out, void* stream);
+
+typedef struct {
+    float lr, beta1, beta2, eps;
+} seismic_adam_params;
+
+/* One Adam step on fp32 master parameters [512] with moments m, v [512]
+ * from the mean gradient grad_sum / stats[1] (the outputs of
+ * seismic_probe_grad); step counts from 1.  weights_out [512] receives the
+ * updated parameters rounded to bf16 (nearest, ties to even); the padding
+ * entries are kept at 0. */
+int seismic_probe_adam(const float* grad_sum, const float* stats, float* master, float* m, float* v, uint32_t step,
+                       const seismic_adam_params* params, uint16_t* weights_out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -48,25 +48,34 @@ class Index:
         return self._ws[key]
 
     def search(self, queries, k: int, query_cut: int, heap_factor: float, *, stats: bool = False,
-               prefix_stride: int | None = None, stream=None, ws=None):
+               prefix_stride: int | None = None, stream=None, ws=None, probe=None, probe_tau: float = 0.0,
+               trace: bool = False):
         """Batched search.  ``queries`` is a binding.Csr (host or device).
         Returns torch tensors on the current device (ids, scores[, prefix,
-        counters])."""
+        counters[, list_hmin, list_term]]).  probe: device tensor of
+        binding.PROBE_WORDS bf16 words (learned block probe) or None."""
         import torch
         nq = int(queries.n_rows)
         dev = torch.device("cuda", torch.cuda.current_device())
         ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
         sc = torch.empty((nq, k), dtype=torch.float32, device=dev)
-        prefix = counters = None
+        prefix = counters = hmin = term = None
+        stats = stats or trace
         if stats:
             stride = prefix_stride or max(1, query_cut if query_cut > 0 else binding.MAX_QUERY_NNZ)
             prefix = torch.zeros((nq, stride), dtype=torch.int16, device=dev)
             counters = torch.zeros((nq, 8), dtype=torch.int64, device=dev)
+            if trace:
+                hmin = torch.empty((nq, stride), dtype=torch.float32, device=dev)
+                term = torch.empty((nq, stride), dtype=torch.int32, device=dev)
         else:
             stride = 0
         w = ws if ws is not None else self.workspace(max(nq, 1), max(k, 1))
         binding.seismic_search_batch(self.handle, w, queries, k, query_cut, heap_factor, ids, sc,
-                                     prefix, stride, counters, stream)
+                                     prefix, stride, counters, stream, probe=probe, probe_tau=probe_tau,
+                                     list_hmin=hmin, list_term=term)
+        if trace:
+            return ids, sc, prefix, counters, hmin, term
         if stats:
             return ids, sc, prefix, counters
         return ids, sc

@@ -42,7 +42,17 @@ class BuildParams(ctypes.Structure):
 
 class SearchParams(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("query_cut", ctypes.c_uint32), ("heap_factor", ctypes.c_float),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("probe", ctypes.c_void_p), ("probe_tau", ctypes.c_double)]
+
+
+class ProbeLoss(ctypes.Structure):
+    _fields_ = [("pos_weight", ctypes.c_float), ("neg_weight", ctypes.c_float),
+                ("neg_weight_per_doc", ctypes.c_float), ("reserved", ctypes.c_uint32)]
+
+
+class AdamParams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -56,7 +66,10 @@ class TuneResult(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("prefix", ctypes.c_void_p), ("prefix_stride", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("counters", ctypes.c_void_p)]
+                ("counters", ctypes.c_void_p), ("list_hmin", ctypes.c_void_p), ("list_term", ctypes.c_void_p)]
+
+
+PROBE_WORDS = 512
 
 
 def load():
@@ -87,6 +100,11 @@ def load():
         "seismic_autotune": ([vp, vp, P(Csr), P(SearchParams), vp, vp, u32, vp, u32, P(u32), vp], i32),
         "seismic_search_batch": ([vp, vp, P(Csr), P(SearchParams), vp, vp, P(Stats), vp], i32),
         "exact_topk": ([vp, P(Csr), u32, vp, vp, vp], i32),
+        "seismic_probe_collect": ([vp, P(Csr), vp, vp, u32, vp, u32, u32, vp, vp, vp], i32),
+        "seismic_probe_trainer_create": ([i32, u32, P(vp)], i32),
+        "seismic_probe_trainer_free": ([vp], None),
+        "seismic_probe_grad": ([vp, vp, vp, vp, u32, P(ProbeLoss), vp, vp, vp, vp], i32),
+        "seismic_probe_adam": ([vp, vp, vp, vp, vp, u32, P(AdamParams), vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -200,11 +218,17 @@ def seismic_workspace_get_config(ws, n_queries: int) -> dict:
     return {"threads": c.threads, "blocks_per_cu": c.blocks_per_cu, "window": c.window}
 
 
+def _params(k, query_cut, heap_factor, flags=0, probe=None, probe_tau=0.0):
+    p = SearchParams(k, query_cut, heap_factor, flags, _ptr(probe), float(probe_tau))
+    p._keep = probe
+    return p
+
+
 def seismic_autotune(handle, ws, queries: Csr, k: int, query_cut: int, heap_factor: float, out_ids, out_scores,
-                     reps: int = 3, stream=None, max_results: int = 256):
+                     reps: int = 3, stream=None, max_results: int = 256, probe=None, probe_tau: float = 0.0):
     """Time every launch shape on this batch, keep the fastest for its
     batch-size bucket; returns the list of (config, ms)."""
-    p = SearchParams(k, query_cut, heap_factor, 0)
+    p = _params(k, query_cut, heap_factor, 0, probe, probe_tau)
     res = (TuneResult * max_results)()
     n = ctypes.c_uint32(0)
     _check(load().seismic_autotune(handle, ws, ctypes.byref(queries), ctypes.byref(p), _ptr(out_ids), _ptr(out_scores),
@@ -215,10 +239,13 @@ def seismic_autotune(handle, ws, queries: Csr, k: int, query_cut: int, heap_fact
 
 def seismic_search_batch(handle, ws, queries: Csr, k: int, query_cut: int, heap_factor: float,
                          out_ids, out_scores, prefix=None, prefix_stride: int = 0, counters=None,
-                         stream=None, flags: int = 0):
-    p = SearchParams(k, query_cut, heap_factor, flags)
-    st = Stats(_ptr(prefix), prefix_stride, 0, _ptr(counters))
-    use_stats = prefix is not None or counters is not None
+                         stream=None, flags: int = 0, probe=None, probe_tau: float = 0.0,
+                         list_hmin=None, list_term=None):
+    """probe: device tensor of PROBE_WORDS bf16 words (int16/uint16/bfloat16)
+    or None; list_hmin (float32) / list_term (int32) [n * prefix_stride]."""
+    p = _params(k, query_cut, heap_factor, flags, probe, probe_tau)
+    st = Stats(_ptr(prefix), prefix_stride, 0, _ptr(counters), _ptr(list_hmin), _ptr(list_term))
+    use_stats = any(x is not None for x in (prefix, counters, list_hmin, list_term))
     _check(load().seismic_search_batch(handle, ws, ctypes.byref(queries), ctypes.byref(p), _ptr(out_ids),
                                        _ptr(out_scores), ctypes.byref(st) if use_stats else None,
                                        _stream_handle(stream)))
@@ -227,3 +254,37 @@ def seismic_search_batch(handle, ws, queries: Csr, k: int, query_cut: int, heap_
 def exact_topk(handle, queries: Csr, k: int, out_ids, out_scores, stream=None):
     _check(load().exact_topk(handle, ctypes.byref(queries), k, _ptr(out_ids), _ptr(out_scores),
                              _stream_handle(stream)))
+
+
+# ------------------------------------------------------- learned block probe
+
+def seismic_probe_collect(handle, queries: Csr, list_term, list_hmin, stride: int, exact_ids, exact_k: int,
+                          max_blocks: int, out_feat, out_label, stream=None):
+    _check(load().seismic_probe_collect(handle, ctypes.byref(queries), _ptr(list_term), _ptr(list_hmin), stride,
+                                        _ptr(exact_ids), exact_k, max_blocks, _ptr(out_feat), _ptr(out_label),
+                                        _stream_handle(stream)))
+
+
+def seismic_probe_trainer_create(device: int, max_batch: int) -> int:
+    t = ctypes.c_void_p()
+    _check(load().seismic_probe_trainer_create(device, max_batch, ctypes.byref(t)))
+    return t.value
+
+
+def seismic_probe_trainer_free(trainer):
+    if trainer:
+        load().seismic_probe_trainer_free(trainer)
+
+
+def seismic_probe_grad(trainer, feat, label, order, n: int, weights, grad_out, stats_out, pos_weight: float = 1.0,
+                       neg_weight: float = 1.0, neg_weight_per_doc: float = 0.0, stream=None):
+    lp = ProbeLoss(pos_weight, neg_weight, neg_weight_per_doc, 0)
+    _check(load().seismic_probe_grad(trainer, _ptr(feat), _ptr(label), _ptr(order), n, ctypes.byref(lp),
+                                     _ptr(weights), _ptr(grad_out), _ptr(stats_out), _stream_handle(stream)))
+
+
+def seismic_probe_adam(grad_sum, stats, master, m, v, step: int, weights_out, lr: float = 1e-3,
+                       beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+    ap = AdamParams(lr, beta1, beta2, eps)
+    _check(load().seismic_probe_adam(_ptr(grad_sum), _ptr(stats), _ptr(master), _ptr(m), _ptr(v), step,
+                                     ctypes.byref(ap), _ptr(weights_out), _stream_handle(stream)))

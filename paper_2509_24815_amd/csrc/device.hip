@@ -6,33 +6,11 @@
 #include <cmath>
 #include <vector>
 
-#include "internal.h"
-#include "search_kernels.h"
+#include "device_internal.h"
+#include "probe.h"
 
 using namespace seismic;
 using seismic_dev::DevIdx;
-
-#define HIP_TRY(call)                                                                     \
-    do {                                                                                  \
-        hipError_t e_ = (call);                                                           \
-        if (e_ != hipSuccess) return fail(SEISMIC_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
-
-struct DeviceIndex {
-    int device = -1;
-    DevIdx view{};
-    uint32_t sort_cap = 2;
-    size_t smem_limit = 0;
-    std::vector<void*> allocs;
-    // full inverted index for exact search (built on first use)
-    uint64_t* csc_off = nullptr;
-    uint32_t* csc_doc = nullptr;
-    uint16_t* csc_val = nullptr;
-    // staging for host-resident queries of exact search
-    uint64_t* xq_ptr = nullptr;
-    uint32_t* xq_words = nullptr;
-    size_t xq_rows_cap = 0, xq_words_cap = 0;
-};
 
 int device_index_layout(const DeviceIndex* d) { return !d ? 0 : d->view.brow ? 2 : 1; }
 
@@ -51,21 +29,6 @@ void device_index_free(DeviceIndex* d) {
 }
 
 namespace {
-
-class DeviceGuard {
-  public:
-    explicit DeviceGuard(int dev) {
-        ok_ = hipGetDevice(&prev_) == hipSuccess && hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (ok_) (void)hipSetDevice(prev_);
-    }
-    bool ok() const { return ok_; }
-
-  private:
-    int prev_ = 0;
-    bool ok_ = false;
-};
 
 // pad: extra zeroed elements after the data (vector loads may overrun the
 // last group of a section by up to pad elements)
@@ -88,6 +51,8 @@ int upload_vec(DeviceIndex* d, const std::vector<T>& v, const T*& out, size_t pa
     return SEISMIC_OK;
 }
 
+}  // namespace
+
 int grow(void** p, size_t& cap, size_t need, size_t elem) {
     if (need <= cap) return SEISMIC_OK;
     size_t n = std::max(need, cap * 2);
@@ -100,8 +65,6 @@ int grow(void** p, size_t& cap, size_t need, size_t elem) {
     return SEISMIC_OK;
 }
 
-}  // namespace
-
 constexpr int kBuckets = 4;  // batch-size buckets of the launch configuration
 
 struct seismic_workspace {
@@ -111,6 +74,7 @@ struct seismic_workspace {
     int n_cu = 0;
     seismic_launch_config cfg[kBuckets];
     uint32_t* queue = nullptr;  // device counter of the persistent search kernel
+    double* probe_w = nullptr;  // sanitized learned-probe parameters of the current batch
     uint64_t* q_ptr = nullptr;  // staging for host-resident queries
     uint32_t* q_words = nullptr;
     size_t q_rows_cap = 0, q_words_cap = 0;
@@ -137,6 +101,7 @@ int check_params(const seismic_index* index, const seismic_workspace* ws, const 
     if (params->k < 1 || params->k > ws->max_k) return fail(SEISMIC_EINVAL, "search: k = %u outside [1, %u]", params->k, ws->max_k);
     if (!(params->heap_factor > 0.0f)) return fail(SEISMIC_EINVAL, "search: heap_factor must be > 0");
     if (params->flags != 0) return fail(SEISMIC_EINVAL, "search: unknown flags");
+    if (params->probe && !(params->probe_tau == params->probe_tau)) return fail(SEISMIC_EINVAL, "search: probe_tau is NaN");
     if (queries->dim != index->h.dim) return fail(SEISMIC_EINVAL, "search: query dim %u != index dim %u", queries->dim, index->h.dim);
     if (queries->n_rows > ws->max_queries)
         return fail(SEISMIC_EINVAL, "search: %llu queries exceed the workspace (%u)", (unsigned long long)queries->n_rows, ws->max_queries);
@@ -164,6 +129,14 @@ int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64
     a.prefix = stats ? stats->prefix : nullptr;
     a.prefix_stride = stats ? stats->prefix_stride : 0;
     a.counters = stats ? stats->counters : nullptr;
+    a.list_hmin = stats ? stats->list_hmin : nullptr;
+    a.list_term = stats ? stats->list_term : nullptr;
+    a.probe_w = nullptr;
+    a.tau = params->probe_tau;
+    if (params->probe) {
+        HIP_TRY(seismic_dev::launch_probe_prep(params->probe, ws->probe_w, st));
+        a.probe_w = ws->probe_w;
+    }
     const uint32_t nt = cfg.threads;
     size_t smem = seismic_dev::search_smem_bytes(nt, index->h.dim, index->dev->sort_cap, params->k);
     int per_cu = seismic_dev::search_blocks_per_cu(nt, smem);
@@ -292,7 +265,9 @@ int seismic_workspace_create(const seismic_index* index, uint32_t max_queries, u
         return fail(SEISMIC_EHIP, "workspace: cannot query device %d", index->dev->device);
     }
     ws->n_cu = prop.multiProcessorCount;
-    if (hipMalloc((void**)&ws->queue, 256) != hipSuccess) {
+    if (hipMalloc((void**)&ws->queue, 256) != hipSuccess ||
+        hipMalloc((void**)&ws->probe_w, seismic_dev::kProbeWords * sizeof(double)) != hipSuccess) {
+        (void)hipFree(ws->queue);
         delete ws;
         return fail(SEISMIC_ENOMEM, "workspace: device allocation failed");
     }
@@ -304,6 +279,7 @@ void seismic_workspace_free(seismic_workspace* ws) {
     if (!ws) return;
     DeviceGuard g(ws->device);
     (void)hipFree(ws->queue);
+    (void)hipFree(ws->probe_w);
     (void)hipFree(ws->q_ptr);
     (void)hipFree(ws->q_words);
     delete ws;

@@ -1,0 +1,51 @@
+// Host-side declarations shared by the device runtime files of libseismic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+#include "search_kernels.h"
+
+#define HIP_TRY(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) return seismic::fail(SEISMIC_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+struct DeviceIndex {
+    int device = -1;
+    seismic_dev::DevIdx view{};
+    uint32_t sort_cap = 2;
+    size_t smem_limit = 0;
+    std::vector<void*> allocs;
+    // full inverted index for exact search (built on first use)
+    uint64_t* csc_off = nullptr;
+    uint32_t* csc_doc = nullptr;
+    uint16_t* csc_val = nullptr;
+    // staging for host-resident queries of exact search
+    uint64_t* xq_ptr = nullptr;
+    uint32_t* xq_words = nullptr;
+    size_t xq_rows_cap = 0, xq_words_cap = 0;
+};
+
+// Makes a device current for the lifetime of the object.
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev) {
+        ok_ = hipGetDevice(&prev_) == hipSuccess && hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (ok_) (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return ok_; }
+
+  private:
+    int prev_ = 0;
+    bool ok_ = false;
+};
+
+// Grows a device buffer to at least need elements (contents are dropped).
+int grow(void** p, size_t& cap, size_t need, size_t elem);

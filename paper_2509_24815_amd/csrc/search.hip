@@ -27,7 +27,12 @@
 //         the list; an evaluated block's documents are folded into the LDS
 //         top-k.  Replaying in order keeps every decision identical to the
 //         sequential algorithm; blocks gathered past a stop are wasted work.
+//      With a learned probe, a list whose traversal starts with a full heap
+//      instead evaluates exactly the blocks whose probe logit (computed once,
+//      from the heap minimum at the list's start) is >= tau: b. keeps those
+//      blocks, nothing is sorted and c. makes no prune decisions.
 #include "device_common.h"
+#include "probe.h"
 #include "search_kernels.h"
 
 namespace seismic_dev {
@@ -315,6 +320,15 @@ __device__ inline void fold_slot(const SearchLds<NT>& L, TopK<NT>& top, uint32_t
     if (nc) top.merge(nc);
 }
 
+// Learned-probe decision for one block (kept out of line: the search's
+// register budget is set by its gather phase, not by this rarely used path).
+__device__ __noinline__ bool probe_keeps(const SearchArgs& a, float r, double h0, uint32_t n_docs, uint32_t n_q,
+                                         uint32_t ci) {
+    double f[kProbeIn];
+    probe_features(r, h0, n_docs, n_q, ci, f);
+    return probe_logit(a.probe_w, f) >= a.tau;
+}
+
 struct Counters {
     uint64_t sum = 0, blocks = 0, eval = 0, docs = 0, tests = 0, nnz = 0;
 };
@@ -322,7 +336,7 @@ struct Counters {
 // Steps 2a-2c for every cut list of query qi.
 template <int NT, typename Look>
 __device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>& top, const Look& look, uint32_t qi,
-                          uint32_t ncut, Counters& C) {
+                          uint32_t ncut, uint32_t nvalid, Counters& C) {
     const int tid = threadIdx.x;
     const DevIdx& ix = a.ix;
     const uint32_t W = a.window;
@@ -330,6 +344,10 @@ __device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>&
         const uint32_t t = L.cut[ci];
         const uint32_t b0 = ix.list_off[t], b1 = ix.list_off[t + 1];
         const uint32_t nb = b1 - b0;
+        if (tid == 0 && ci < a.prefix_stride) {
+            if (a.list_term) a.list_term[(size_t)qi * a.prefix_stride + ci] = t;
+            if (a.list_hmin) a.list_hmin[(size_t)qi * a.prefix_stride + ci] = top.full() ? top.min_score() : -1.0f;
+        }
         if (nb == 0) {
             if (a.prefix && tid == 0 && ci < a.prefix_stride) a.prefix[(size_t)qi * a.prefix_stride + ci] = 0;
             continue;
@@ -363,6 +381,7 @@ __device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>&
         // ---------------------------------------- b. prefilter + sort
         const bool full0 = top.full();
         const double hmin0 = full0 ? (double)top.min_score() : 0.0;
+        const bool learned = full0 && a.probe_w != nullptr;
         uint32_t nsurv = 0;
         for (uint32_t c = 0; c < nb; c += NT) {
             const uint32_t i = c + tid;
@@ -370,7 +389,11 @@ __device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>&
             bool keep = false;
             if (i < nb) {
                 rv = (float)((double)ix.blk_m[b0 + i] * L.A[i] + (double)ix.blk_delta[b0 + i] * L.B[i]);
-                keep = !(full0 && (double)rv * (double)a.hf < hmin0);
+                if (learned) {
+                    keep = probe_keeps(a, rv, hmin0, ix.blk_post_off[b0 + i + 1] - ix.blk_post_off[b0 + i], nvalid, ci);
+                } else {
+                    keep = !(full0 && (double)rv * (double)a.hf < hmin0);
+                }
             }
             uint32_t cnt;
             const uint32_t at = block_exscan<NT>(keep ? 1u : 0u, L.scratch, &cnt);
@@ -381,7 +404,7 @@ __device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>&
         while (Pl < nsurv) Pl <<= 1;
         for (uint32_t i = nsurv + tid; i < Pl; i += NT) { L.r[i] = -INFINITY; L.ord[i] = 0xFFFFu; }
         __syncthreads();
-        if (nsurv > 1) {
+        if (nsurv > 1 && !learned) {
             for (uint32_t kk = 2; kk <= Pl; kk <<= 1) {
                 for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
                     for (uint32_t i = tid; i < Pl; i += NT) {
@@ -419,7 +442,7 @@ __device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>&
             }
             if (tot > (uint32_t)NT) {
                 // a single block larger than a chunk: evaluated alone
-                if (top.full()) {
+                if (!learned && top.full()) {
                     ++C.tests;
                     if ((double)L.r[pos] * (double)a.hf < (double)top.min_score()) { stop = true; break; }
                 }
@@ -444,7 +467,7 @@ __device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>&
             __syncthreads();
             gather_and_score<NT, Look>(ix, L, look, tot, nwb, 0);
             for (uint32_t s = 0; s < nwb; ++s) {
-                if (top.full()) {
+                if (!learned && top.full()) {
                     ++C.tests;
                     if ((double)L.r[pos + s] * (double)a.hf < (double)top.min_score()) { stop = true; break; }
                 }
@@ -455,7 +478,8 @@ __device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>&
             pos += stop ? 0u : nwb;
             __syncthreads();
         }
-        if (!stop && nsurv < nb) ++C.tests;  // the first dropped block ends the list
+        if (learned) C.tests += nb;                     // one probe decision per block
+        else if (!stop && nsurv < nb) ++C.tests;        // the first dropped block ends the list
         if (a.prefix && tid == 0 && ci < a.prefix_stride)
             a.prefix[(size_t)qi * a.prefix_stride + ci] = (uint16_t)min(evaluated, 65535u);
         C.eval += evaluated;
@@ -563,10 +587,10 @@ __global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
         Counters C;
         if (u8mode) {
             LookU8 look{L.region, L.qv};
-            run_lists<NT, LookU8>(a, L, top, look, qi, ncut, C);
+            run_lists<NT, LookU8>(a, L, top, look, qi, ncut, nvalid, C);
         } else {
             LookBits look{L.bq};
-            run_lists<NT, LookBits>(a, L, top, look, qi, ncut, C);
+            run_lists<NT, LookBits>(a, L, top, look, qi, ncut, nvalid, C);
         }
 
         // ------------------------------------------------------------ output
@@ -579,8 +603,11 @@ __global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
                 a.out_scores[(size_t)qi * a.k + i] = have ? H[i] : -INFINITY;
             }
         }
-        if (a.prefix)
-            for (uint32_t i = ncut + tid; i < a.prefix_stride; i += NT) a.prefix[(size_t)qi * a.prefix_stride + i] = 0;
+        for (uint32_t i = ncut + tid; i < a.prefix_stride; i += NT) {
+            if (a.prefix) a.prefix[(size_t)qi * a.prefix_stride + i] = 0;
+            if (a.list_term) a.list_term[(size_t)qi * a.prefix_stride + i] = 0xFFFFFFFFu;
+            if (a.list_hmin) a.list_hmin[(size_t)qi * a.prefix_stride + i] = -1.0f;
+        }
         if (a.counters) {
             const unsigned long long v = wave_sum((unsigned long long)C.nnz);
             unsigned long long* red = (unsigned long long*)L.crs;  // union region is free here

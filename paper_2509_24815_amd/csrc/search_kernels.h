@@ -30,6 +30,10 @@ struct SearchArgs {
     uint16_t* prefix;
     uint32_t prefix_stride;
     uint64_t* counters;
+    float* list_hmin;       // [nq * prefix_stride] heap minimum at each cut list's start (-1: not full), or NULL
+    uint32_t* list_term;    // [nq * prefix_stride] term of each cut list (0xFFFFFFFF past the cut), or NULL
+    const double* probe_w;  // sanitized learned-probe parameters (fp64), or NULL for the heap_factor rule
+    double tau;             // probe threshold: a probe-owned list evaluates the blocks with logit >= tau
 };
 
 // nt = threads per workgroup (256 or 512); grid = number of persistent workgroups.
