@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--index-cache", default=None, help="load the index from this file if present, else build and save")
     ap.add_argument("--plain-rows", action="store_true", help="search the forward rows in place (no block-major copies)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--probe", default=os.path.join(ROOT, "paper_2509_24815_amd", "probes", "probe_1m.npy"),
+                    help="learned block-probe weights to evaluate beside the heap_factor rule ('' = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -199,33 +201,53 @@ def main():
             tie.append(min(n, int((asc[a != 0xFFFFFFFF] >= kth).sum())) / n)
         return float(np.mean(strict)), float(np.mean(tie))
 
-    def run(hf, with_stats):
+    def run(hf, with_stats, probe=None, tau=0.0):
         binding.seismic_search_batch(ix.handle, ws, qcsr, k, cut, hf, out_ids, out_sc,
                                      prefix if with_stats else None, cut if with_stats else 0,
-                                     counters if with_stats else None, stream)
+                                     counters if with_stats else None, stream, probe=probe, probe_tau=tau)
 
-    # sweep heap_factor (Alg. 2 skip rule r * hf < heap.min: larger hf prunes less)
-    sweep = []
-    hfs = [args.hf] if args.hf else list(W["hfs"])
-    chosen = None
-    for hf in hfs:
-        run(hf, True)
+    def measure(hf, probe=None, tau=0.0):
+        run(hf, True, probe, tau)
         torch.cuda.synchronize()
         ts = time.time()
         for _ in range(2):
-            run(hf, False)
+            run(hf, False, probe, tau)
         torch.cuda.synchronize()
         dt = (time.time() - ts) / 2
         rs, rt = recall_of(out_ids.cpu().numpy().view(np.uint32), out_sc.cpu().numpy())
         cnt = counters.cpu().numpy()
-        point = dict(hf=hf, recall=round(rs, 4), recall_tie_aware=round(rt, 4), qps=round(nq / dt, 1),
-                     docs_evaluated=float(cnt[:, 3].mean()), blocks_evaluated=float(cnt[:, 2].mean()))
-        sweep.append(point)
-        log(f"[bench] sweep {point}")
-        if chosen is None and rs >= args.recall:
-            chosen = hf
-        if chosen is not None and not args.hf:
-            break
+        return dict(recall=round(rs, 4), recall_tie_aware=round(rt, 4), qps=round(nq / dt, 1),
+                    docs_evaluated=float(cnt[:, 3].mean()), blocks_evaluated=float(cnt[:, 2].mean()))
+
+    def search_grid(values, key, fn):
+        """Walk values from most to least pruning; stop at the first point
+        that reaches the recall target, then bisect once between it and the
+        previous point.  Returns (chosen value, points)."""
+        pts, chosen, prev = [], None, None
+        for v in values:
+            pt = dict({key: v}, **fn(v))
+            pts.append(pt)
+            log(f"[bench] sweep {pt}")
+            if pt["recall"] >= args.recall:
+                chosen = v
+                break
+            prev = v
+        if chosen is not None and prev is not None:
+            mid = round((prev + chosen) / 2, 4)
+            pt = dict({key: mid}, **fn(mid))
+            pts.append(pt)
+            log(f"[bench] sweep {pt}")
+            if pt["recall"] >= args.recall and pt["qps"] > next(p for p in pts if p[key] == chosen)["qps"]:
+                chosen = mid
+        return chosen, pts
+
+    # sweep heap_factor (Alg. 2 skip rule r * hf < heap.min: larger hf prunes less)
+    if args.hf:
+        sweep = [dict(hf=args.hf, **measure(args.hf))]
+        log(f"[bench] sweep {sweep[0]}")
+        chosen = args.hf
+    else:
+        chosen, sweep = search_grid(list(W["hfs"]), "hf", measure)
     if chosen is None:
         chosen = max(sweep, key=lambda p: p["recall"])["hf"]
         log(f"[bench] no swept heap_factor reached Recall@10 {args.recall}; using the best ({chosen})")
@@ -265,6 +287,36 @@ def main():
     log(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step, {qps:.0f} QPS, wall {wall:.2f} s, "
         f"{achieved:.1f} GB/s algorithmic")
 
+    plain_ids = out_ids.cpu().numpy().view(np.uint32).copy()  # results of the timed steps
+
+    # learned block probe (lists that start with a full heap), heap_factor rule elsewhere
+    learned = None
+    if args.probe and os.path.exists(args.probe):
+        from paper_2509_24815_amd import probe as P
+        pw = P.to_device(P.load(args.probe), dev)
+        taus = [2.0, 1.5, 1.0, 0.75, 0.5, 0.25, 0.0, -0.25, -0.5, -1.0, -1.5, -2.0, -3.0]
+        tau, lpts = search_grid(taus, "tau", lambda t: measure(chosen, pw, t))
+        if tau is not None:
+            lp = next(p for p in lpts if p["tau"] == tau)
+            for _ in range(args.warmup):
+                run(chosen, False, pw, tau)
+            torch.cuda.synchronize()
+            l0, l1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            l0.record(stream)
+            for _ in range(args.steps):
+                run(chosen, False, pw, tau)
+            l1.record(stream)
+            torch.cuda.synchronize()
+            lms = l0.elapsed_time(l1) / args.steps
+            learned = {"probe": os.path.relpath(args.probe, ROOT), "tau": tau, "heap_factor_fallback": chosen,
+                       "recall_at_10": lp["recall"], "qps": round(nq / (lms / 1e3), 1), "ms_per_step": round(lms, 4),
+                       "docs_evaluated": lp["docs_evaluated"], "qps_vs_heap_factor_rule": round(lms and ms_per_step / lms, 4),
+                       "docs_vs_heap_factor_rule": round(lp["docs_evaluated"] / point["docs_evaluated"], 4),
+                       "sweep": lpts}
+        else:
+            learned = {"probe": os.path.relpath(args.probe, ROOT), "reached_target": False, "sweep": lpts}
+        log(f"[bench] learned probe {learned}")
+
     if args.profile_copy:
         n = 1 << 28
         a = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -292,7 +344,7 @@ def main():
         tc = time.time()
         r = ref.pruned_search(sample, k, cut, chosen, nthreads=threads, c_cap=cut)
         cpu_s = time.time() - tc
-        g_ids = out_ids.cpu().numpy().view(np.uint32)[:n_sample]
+        g_ids = plain_ids[:n_sample]
         match = float((r["ids"] == g_ids).all(axis=1).mean())
         cpu = {"value": round(n_sample / cpu_s, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
                "sample": f"first {n_sample} of the {nq} queries, heap_factor {chosen}, {cpu_s:.1f} s",
@@ -320,7 +372,7 @@ def main():
                    "recall_at_10": point["recall"], "recall_target": args.recall,
                    "index_build_s": None if build_s is None else round(build_s, 1),
                    "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
-                   "sweep": sweep},
+                   "sweep": sweep, "learned_probe": learned},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "traffic_frac": None if traffic is None else round(traffic / (ms_per_step / 1e3) / 1e9

@@ -320,13 +320,28 @@ __device__ inline void fold_slot(const SearchLds<NT>& L, TopK<NT>& top, uint32_t
     if (nc) top.merge(nc);
 }
 
-// Learned-probe decision for one block (kept out of line: the search's
-// register budget is set by its gather phase, not by this rarely used path).
-__device__ __noinline__ bool probe_keeps(const SearchArgs& a, float r, double h0, uint32_t n_docs, uint32_t n_q,
-                                         uint32_t ci) {
+// Learned-probe decision for one block.  Kept out of line (the search's
+// register budget is set by its gather phase); the parameter pointer is
+// made wave-uniform and read through the constant address space, so the
+// 449 parameters come in with scalar loads.
+typedef const double __attribute__((address_space(4)))* ConstDoublePtr;
+
+__device__ __noinline__ bool probe_keeps(const double* w, double tau, float r, double h0, uint32_t n_docs,
+                                         uint32_t n_q, uint32_t ci) {
+    const uint64_t pv = (uint64_t)w;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)pv);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(pv >> 32));
+    const ConstDoublePtr W = (ConstDoublePtr)((hi << 32) | lo);
     double f[kProbeIn];
     probe_features(r, h0, n_docs, n_q, ci, f);
-    return probe_logit(a.probe_w, f) >= a.tau;
+    double z = W[kProbeB2];
+    for (uint32_t l = 0; l < kProbeHidden; ++l) {
+        double x = W[kProbeB1 + l];
+#pragma unroll
+        for (uint32_t i = 0; i < kProbeIn; ++i) x = fma(W[l * kProbeIn + i], f[i], x);
+        z = fma(W[kProbeW2 + l], probe_q(x, 0x1p-8, 256.0), z);
+    }
+    return z >= tau;
 }
 
 struct Counters {
@@ -390,7 +405,8 @@ __device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>&
             if (i < nb) {
                 rv = (float)((double)ix.blk_m[b0 + i] * L.A[i] + (double)ix.blk_delta[b0 + i] * L.B[i]);
                 if (learned) {
-                    keep = probe_keeps(a, rv, hmin0, ix.blk_post_off[b0 + i + 1] - ix.blk_post_off[b0 + i], nvalid, ci);
+                    keep = probe_keeps(a.probe_w, a.tau, rv, hmin0, ix.blk_post_off[b0 + i + 1] - ix.blk_post_off[b0 + i],
+                                       nvalid, ci);
                 } else {
                     keep = !(full0 && (double)rv * (double)a.hf < hmin0);
                 }
