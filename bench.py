@@ -92,6 +92,33 @@ def alg_bytes(counters: np.ndarray, q_nnz: np.ndarray, k: int) -> np.ndarray:
             + 4 * c[:, 4] + 8 * k)
 
 
+def serve_run(binding, ix, qs, rate, seconds, k, cut, hf, probe, tau, max_batch=1024, slots=4):
+    """Open-loop Poisson arrivals at `rate` queries/s for `seconds` (queries
+    cycle through the batch), served by the library's serving loop.
+    Latency = completion - arrival."""
+    n = int(rate * seconds)
+    rows = np.arange(n) % qs.n_rows
+    sub = qs.subset(rows)
+    arrivals = 0.2 + np.cumsum(np.random.default_rng(4).exponential(1.0 / rate, n))
+    sv = binding.seismic_server_create(ix.handle, k, cut, hf, max_batch=max_batch, n_slots=slots, probe=probe,
+                                       probe_tau=tau)
+    try:
+        t0 = binding.seismic_server_clock(sv)
+        first = binding.seismic_server_submit_batch(sv, binding.host_csr(sub.row_ptr, sub.words, sub.dim),
+                                                    t0 + arrivals)
+        binding.seismic_server_wait_all(sv, 600.0)
+        _, _, lat = binding.seismic_server_results(sv, first, n, k)
+        st = binding.seismic_server_stats(sv)
+    finally:
+        binding.seismic_server_free(sv)
+    span = float(np.max(arrivals + lat) - arrivals[0])
+    return {"offered_qps": rate, "queries": n, "sustained_qps": round(n / span, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "batches": st["batches"], "mean_batch": round(n / max(st["batches"], 1), 1),
+            "max_inflight": st["max_inflight"], "slots": slots, "max_batch": max_batch}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +134,8 @@ def main():
     ap.add_argument("--index-cache", default=None, help="load the index from this file if present, else build and save")
     ap.add_argument("--plain-rows", action="store_true", help="search the forward rows in place (no block-major copies)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per serving rate")
     ap.add_argument("--probe", default=os.path.join(ROOT, "paper_2509_24815_amd", "probes", "probe_1m.npy"),
                     help="learned block-probe weights to evaluate beside the heap_factor rule ('' = skip)")
     args = ap.parse_args()
@@ -317,6 +346,21 @@ def main():
             learned = {"probe": os.path.relpath(args.probe, ROOT), "reached_target": False, "sweep": lpts}
         log(f"[bench] learned probe {learned}")
 
+    # serving loop: Poisson arrivals, continuous batching over 4 slots
+    serving = None
+    if not args.no_serve:
+        serving = {}
+        rates = (5000.0, 20000.0, 50000.0)
+        forms = [("heap_factor_rule", None, 0.0)]
+        if learned and learned.get("tau") is not None:
+            forms.append(("learned_probe", pw, learned["tau"]))
+        for name, pr, tau in forms:
+            rows = []
+            for rate in rates:
+                rows.append(serve_run(binding, ix, qs, rate, args.serve_seconds, k, cut, chosen, pr, tau))
+                log(f"[bench] serving {name} {rows[-1]}")
+            serving[name] = rows
+
     if args.profile_copy:
         n = 1 << 28
         a = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -373,6 +417,7 @@ def main():
                    "index_build_s": None if build_s is None else round(build_s, 1),
                    "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
                    "sweep": sweep, "learned_probe": learned},
+        "serving": serving,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "traffic_frac": None if traffic is None else round(traffic / (ms_per_step / 1e3) / 1e9

@@ -301,6 +301,55 @@ typedef struct {
 int seismic_probe_adam(const float* grad_sum, const float* stats, float* master, float* m, float* v, uint32_t step,
                        const seismic_adam_params* params, uint16_t* weights_out, void* stream);
 
+/* ------------------------------------------------------ serving loop
+ * Continuous batching (not in the paper).  A server owns n_slots batch
+ * slots, each with its own stream, search workspace, device buffers and
+ * pinned staging for up to max_batch queries / max_batch_nnz nonzeros; the
+ * index stays resident.  A dispatcher thread forms a batch whenever a slot
+ * is free from the requests that have arrived (in submission order, up to
+ * the slot's capacity), launches it (copy in, seismic_search_batch, copy
+ * out) and delivers results when its event completes; batches on different
+ * slots overlap on the device.  Each query's result is exactly what
+ * seismic_search_batch gives for it alone (queries are independent).
+ * search.probe, when set, must stay valid until the server is freed. */
+typedef struct seismic_server seismic_server;
+typedef struct {
+    seismic_search_params search;
+    uint32_t max_batch;          /* queries per batch */
+    uint32_t n_slots;            /* batches in flight, 1..64 */
+    uint32_t max_batch_nnz;      /* query nonzeros per batch, >= SEISMIC_MAX_QUERY_NNZ */
+    uint32_t reserved;
+    seismic_launch_config launch; /* threads = 0: the workspace default */
+} seismic_server_params;
+
+int seismic_server_create(const seismic_index* index, const seismic_server_params* params, seismic_server** out);
+/* Seconds since the server was created (its clock for not_before). */
+double seismic_server_clock(const seismic_server* server);
+/* Queue one query (host words, validated: EINVAL) that may be admitted from
+ * server time not_before on (0 = now; must not decrease between calls).
+ * *ticket identifies it; tickets count from 0 in submission order.
+ * Thread-safe. */
+int seismic_server_submit(seismic_server* server, const uint32_t* words, uint32_t nnz, double not_before,
+                          uint64_t* ticket);
+/* Queue the rows of a host CSR (validated) at once; not_before [n_rows]
+ * (nullable = all now) non-decreasing; tickets are *first_ticket + row. */
+int seismic_server_submit_batch(seismic_server* server, const seismic_csr* queries, const double* not_before,
+                                uint64_t* first_ticket);
+/* Results of tickets [first_ticket, first_ticket + n), all done (ESTATE
+ * otherwise): ids/scores [n * k] host, latency [n] seconds; each nullable. */
+int seismic_server_results(seismic_server* server, uint64_t first_ticket, uint64_t n, uint32_t* ids, float* scores,
+                           double* latency);
+/* 1 and the result (ids/scores [k] host, nullable; latency = completion -
+ * max(submission, not_before) in seconds) when done, 0 while pending, < 0 on
+ * error (a failed batch stops the server). */
+int seismic_server_poll(seismic_server* server, uint64_t ticket, uint32_t* ids, float* scores, double* latency);
+/* Block until every submitted query is done (ESTATE after timeout_s). */
+int seismic_server_wait_all(seismic_server* server, double timeout_s);
+/* out = submitted, completed, batches launched, most queries in flight. */
+int seismic_server_stats(const seismic_server* server, uint64_t out[4]);
+/* Stops admitting, waits for launched batches, releases everything. */
+void seismic_server_free(seismic_server* server);
+
 #ifdef __cplusplus
 }
 #endif

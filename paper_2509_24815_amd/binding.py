@@ -60,6 +60,11 @@ class LaunchConfig(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class ServerParams(ctypes.Structure):
+    _fields_ = [("search", SearchParams), ("max_batch", ctypes.c_uint32), ("n_slots", ctypes.c_uint32),
+                ("max_batch_nnz", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("launch", LaunchConfig)]
+
+
 class TuneResult(ctypes.Structure):
     _fields_ = [("cfg", LaunchConfig), ("ms", ctypes.c_float), ("reserved", ctypes.c_uint32)]
 
@@ -105,6 +110,15 @@ def load():
         "seismic_probe_trainer_free": ([vp], None),
         "seismic_probe_grad": ([vp, vp, vp, vp, u32, P(ProbeLoss), vp, vp, vp, vp], i32),
         "seismic_probe_adam": ([vp, vp, vp, vp, vp, u32, P(AdamParams), vp, vp], i32),
+        "seismic_server_create": ([vp, P(ServerParams), P(vp)], i32),
+        "seismic_server_clock": ([vp], ctypes.c_double),
+        "seismic_server_submit": ([vp, vp, u32, ctypes.c_double, P(u64)], i32),
+        "seismic_server_poll": ([vp, u64, vp, vp, P(ctypes.c_double)], i32),
+        "seismic_server_submit_batch": ([vp, P(Csr), vp, P(u64)], i32),
+        "seismic_server_results": ([vp, u64, u64, vp, vp, vp], i32),
+        "seismic_server_wait_all": ([vp, ctypes.c_double], i32),
+        "seismic_server_stats": ([vp, vp], i32),
+        "seismic_server_free": ([vp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -288,3 +302,75 @@ def seismic_probe_adam(grad_sum, stats, master, m, v, step: int, weights_out, lr
     ap = AdamParams(lr, beta1, beta2, eps)
     _check(load().seismic_probe_adam(_ptr(grad_sum), _ptr(stats), _ptr(master), _ptr(m), _ptr(v), step,
                                      ctypes.byref(ap), _ptr(weights_out), _stream_handle(stream)))
+
+
+# ------------------------------------------------------------ serving loop
+
+def seismic_server_create(handle, k: int, query_cut: int, heap_factor: float, max_batch: int = 1024,
+                          n_slots: int = 4, max_batch_nnz: int = 0, probe=None, probe_tau: float = 0.0,
+                          launch: dict | None = None) -> int:
+    """probe (device tensor) must outlive the server."""
+    sp = _params(k, query_cut, heap_factor, 0, probe, probe_tau)
+    lc = LaunchConfig(0, 0, 0, 0) if not launch else LaunchConfig(launch["threads"], launch["blocks_per_cu"],
+                                                                  launch["window"], 0)
+    p = ServerParams(sp, max_batch, n_slots, max_batch_nnz or max(MAX_QUERY_NNZ, 256 * max_batch), 0, lc)
+    s = ctypes.c_void_p()
+    _check(load().seismic_server_create(handle, ctypes.byref(p), ctypes.byref(s)))
+    return s.value
+
+
+def seismic_server_clock(server) -> float:
+    return float(load().seismic_server_clock(server))
+
+
+def seismic_server_submit(server, words: np.ndarray, not_before: float = 0.0) -> int:
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    t = ctypes.c_uint64()
+    _check(load().seismic_server_submit(server, _ptr(w) if len(w) else None, len(w), float(not_before),
+                                        ctypes.byref(t)))
+    return t.value
+
+
+def seismic_server_submit_batch(server, queries: Csr, not_before=None) -> int:
+    """queries: host Csr; not_before: float64 [n_rows] or None.  Returns the
+    first ticket."""
+    nb = None if not_before is None else np.ascontiguousarray(not_before, dtype=np.float64)
+    t = ctypes.c_uint64()
+    _check(load().seismic_server_submit_batch(server, ctypes.byref(queries), None if nb is None else _ptr(nb),
+                                              ctypes.byref(t)))
+    return t.value
+
+
+def seismic_server_results(server, first_ticket: int, n: int, k: int):
+    """(ids uint32 [n, k], scores float32 [n, k], latency float64 [n])."""
+    ids = np.empty((n, k), dtype=np.uint32)
+    sc = np.empty((n, k), dtype=np.float32)
+    lat = np.empty(n, dtype=np.float64)
+    _check(load().seismic_server_results(server, first_ticket, n, _ptr(ids), _ptr(sc), _ptr(lat)))
+    return ids, sc, lat
+
+
+def seismic_server_poll(server, ticket: int, k: int):
+    """None while pending, else (ids uint32[k], scores float32[k], latency s)."""
+    ids = np.empty(k, dtype=np.uint32)
+    sc = np.empty(k, dtype=np.float32)
+    lat = ctypes.c_double()
+    rc = load().seismic_server_poll(server, ticket, _ptr(ids), _ptr(sc), ctypes.byref(lat))
+    if rc < 0:
+        _check(rc)
+    return None if rc == 0 else (ids, sc, lat.value)
+
+
+def seismic_server_wait_all(server, timeout_s: float = 600.0):
+    _check(load().seismic_server_wait_all(server, timeout_s))
+
+
+def seismic_server_stats(server) -> dict:
+    out = np.zeros(4, dtype=np.uint64)
+    _check(load().seismic_server_stats(server, _ptr(out)))
+    return dict(zip(("submitted", "completed", "batches", "max_inflight"), (int(x) for x in out)))
+
+
+def seismic_server_free(server):
+    if server:
+        load().seismic_server_free(server)

@@ -1,0 +1,387 @@
+// Serving loop: continuous batching of arriving queries over a fixed set of
+// batch slots.  Host code only (HIP runtime API); the search itself is
+// seismic_search_batch.
+//
+// A slot owns everything one in-flight batch needs - a search workspace,
+// device buffers for the batch's queries and results, pinned host staging
+// and an event, all on its own stream - so admission is by scratch memory:
+// a batch is formed only when a slot is free, from the requests that have
+// arrived, in submission order, up to the slot's query and nonzero
+// capacity.  Batches on different slots overlap on the device.  A
+// dispatcher thread admits batches, launches them and delivers finished
+// results; callers submit and poll from any thread.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "device_internal.h"
+
+using namespace seismic;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    std::vector<uint32_t> words;
+    double not_before = 0.0;  // server clock (s): earliest admission
+    double arrival = 0.0;     // max(submit time, not_before)
+    double done_at = 0.0;
+    bool done = false;
+    std::vector<uint32_t> ids;
+    std::vector<float> scores;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    seismic_workspace* ws = nullptr;
+    uint64_t* d_ptr = nullptr;
+    uint32_t* d_words = nullptr;
+    uint32_t* d_ids = nullptr;
+    float* d_scores = nullptr;
+    uint64_t* h_ptr = nullptr;   // pinned
+    uint32_t* h_words = nullptr; // pinned
+    uint32_t* h_ids = nullptr;   // pinned
+    float* h_scores = nullptr;   // pinned
+    std::vector<uint64_t> tickets;
+    bool busy = false;
+};
+
+}  // namespace
+
+struct seismic_server {
+    const seismic_index* index = nullptr;
+    seismic_server_params p{};
+    int device = -1;
+    Clock::time_point t0;
+    std::vector<Slot> slots;
+    std::mutex mu;
+    std::condition_variable cv_work;  // new requests or stop
+    std::condition_variable cv_done;  // results delivered
+    std::deque<Request> reqs;         // by ticket
+    uint64_t next_admit = 0;          // first ticket not yet admitted
+    uint64_t completed = 0, batches = 0, max_inflight = 0;
+    bool stop = false;
+    int error = 0;
+    std::string error_msg;
+    std::thread worker;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+void free_slot(Slot& s) {
+    if (s.ws) seismic_workspace_free(s.ws);
+    (void)hipFree(s.d_ptr);
+    (void)hipFree(s.d_words);
+    (void)hipFree(s.d_ids);
+    (void)hipFree(s.d_scores);
+    (void)hipHostFree(s.h_ptr);
+    (void)hipHostFree(s.h_words);
+    (void)hipHostFree(s.h_ids);
+    (void)hipHostFree(s.h_scores);
+    if (s.event) (void)hipEventDestroy(s.event);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    s = Slot();
+}
+
+int make_slot(seismic_server* sv, Slot& s) {
+    const seismic_server_params& p = sv->p;
+    const size_t nq = p.max_batch, nnz = p.max_batch_nnz, nk = (size_t)p.max_batch * p.search.k;
+    HIP_TRY(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&s.event, hipEventDisableTiming));
+    int rc = seismic_workspace_create(sv->index, p.max_batch, p.search.k, &s.ws);
+    if (!rc && p.launch.threads) rc = seismic_workspace_set_config(s.ws, &p.launch);
+    if (rc) return rc;
+    if (hipMalloc((void**)&s.d_ptr, (nq + 1) * 8) != hipSuccess || hipMalloc((void**)&s.d_words, nnz * 4) != hipSuccess ||
+        hipMalloc((void**)&s.d_ids, nk * 4) != hipSuccess || hipMalloc((void**)&s.d_scores, nk * 4) != hipSuccess)
+        return fail(SEISMIC_ENOMEM, "server: device allocation of a slot failed");
+    if (hipHostMalloc((void**)&s.h_ptr, (nq + 1) * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&s.h_words, nnz * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&s.h_ids, nk * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&s.h_scores, nk * 4, hipHostMallocDefault) != hipSuccess)
+        return fail(SEISMIC_ENOMEM, "server: pinned host allocation of a slot failed");
+    return SEISMIC_OK;
+}
+
+// Launch one batch on slot s (called without the lock held).
+int launch(seismic_server* sv, Slot& s, uint32_t nq, uint64_t nnz) {
+    const uint32_t k = sv->p.search.k;
+    HIP_TRY(hipMemcpyAsync(s.d_ptr, s.h_ptr, (nq + 1) * 8, hipMemcpyHostToDevice, s.stream));
+    if (nnz) HIP_TRY(hipMemcpyAsync(s.d_words, s.h_words, nnz * 4, hipMemcpyHostToDevice, s.stream));
+    seismic_csr q{nq, nnz, sv->index->h.dim, 1, s.d_ptr, s.d_words};
+    int rc = seismic_search_batch(sv->index, s.ws, &q, &sv->p.search, s.d_ids, s.d_scores, nullptr, s.stream);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(s.h_ids, s.d_ids, (size_t)nq * k * 4, hipMemcpyDeviceToHost, s.stream));
+    HIP_TRY(hipMemcpyAsync(s.h_scores, s.d_scores, (size_t)nq * k * 4, hipMemcpyDeviceToHost, s.stream));
+    HIP_TRY(hipEventRecord(s.event, s.stream));
+    return SEISMIC_OK;
+}
+
+void run(seismic_server* sv) {
+    DeviceGuard g(sv->device);
+    const uint32_t k = sv->p.search.k;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        bool progress = false;
+        // deliver finished batches
+        for (Slot& s : sv->slots) {
+            if (!s.busy) continue;
+            lk.unlock();
+            hipError_t e = hipEventQuery(s.event);
+            lk.lock();
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) {
+                sv->error = SEISMIC_EHIP;
+                sv->error_msg = std::string("server: batch failed: ") + hipGetErrorString(e);
+                sv->stop = true;
+                break;
+            }
+            const double t = sv->now();
+            for (size_t i = 0; i < s.tickets.size(); ++i) {
+                Request& r = sv->reqs[s.tickets[i]];
+                r.ids.assign(s.h_ids + i * k, s.h_ids + (i + 1) * k);
+                r.scores.assign(s.h_scores + i * k, s.h_scores + (i + 1) * k);
+                r.done_at = t;
+                r.done = true;
+            }
+            sv->completed += s.tickets.size();
+            s.tickets.clear();
+            s.busy = false;
+            progress = true;
+        }
+        if (progress) sv->cv_done.notify_all();
+        if (sv->stop) break;
+        // admit arrived requests into free slots
+        uint64_t inflight = 0;
+        for (Slot& s : sv->slots) {
+            if (s.busy) { inflight += s.tickets.size(); continue; }
+            const double t = sv->now();
+            uint32_t nq = 0;
+            uint64_t nnz = 0;
+            s.h_ptr[0] = 0;
+            while (sv->next_admit < sv->reqs.size() && nq < sv->p.max_batch) {
+                Request& r = sv->reqs[sv->next_admit];
+                if (r.not_before > t) break;
+                if (nnz + r.words.size() > sv->p.max_batch_nnz) break;
+                std::memcpy(s.h_words + nnz, r.words.data(), r.words.size() * 4);
+                nnz += r.words.size();
+                s.h_ptr[++nq] = nnz;
+                s.tickets.push_back(sv->next_admit++);
+            }
+            if (nq == 0) break;
+            s.busy = true;
+            ++sv->batches;
+            inflight += nq;
+            lk.unlock();
+            int rc = launch(sv, s, nq, nnz);
+            lk.lock();
+            if (rc) {
+                sv->error = rc;
+                sv->error_msg = seismic_last_error();
+                sv->stop = true;
+                break;
+            }
+            progress = true;
+        }
+        if (inflight > sv->max_inflight) sv->max_inflight = inflight;
+        if (sv->stop) break;
+        if (!progress) {
+            // sleep until new work, the next scheduled arrival, or a short
+            // poll interval for busy slots
+            double wait = 50e-6;
+            bool any_busy = false;
+            for (Slot& s : sv->slots) any_busy |= s.busy;
+            if (!any_busy) {
+                if (sv->next_admit < sv->reqs.size())
+                    wait = std::max(0.0, sv->reqs[sv->next_admit].not_before - sv->now());
+                else
+                    wait = 0.05;
+            }
+            sv->cv_work.wait_for(lk, std::chrono::duration<double>(wait));
+        }
+    }
+    // drain: wait for launched batches before the slots are released
+    lk.unlock();
+    for (Slot& s : sv->slots)
+        if (s.busy) (void)hipEventSynchronize(s.event);
+    lk.lock();
+    sv->cv_done.notify_all();
+}
+
+}  // namespace
+
+extern "C" {
+
+int seismic_server_create(const seismic_index* index, const seismic_server_params* params, seismic_server** out) {
+    if (!index || !params || !out) return fail(SEISMIC_EINVAL, "server: null argument");
+    *out = nullptr;
+    if (!index->dev) return fail(SEISMIC_ESTATE, "server: index is not on a device");
+    const seismic_server_params& p = *params;
+    if (p.n_slots < 1 || p.n_slots > 64) return fail(SEISMIC_EINVAL, "server: n_slots must be in [1, 64]");
+    if (p.max_batch < 1) return fail(SEISMIC_EINVAL, "server: max_batch must be >= 1");
+    if (p.max_batch_nnz < SEISMIC_MAX_QUERY_NNZ)
+        return fail(SEISMIC_EINVAL, "server: max_batch_nnz must be >= %d", SEISMIC_MAX_QUERY_NNZ);
+    if (p.search.k < 1 || p.search.k > SEISMIC_MAX_K || !(p.search.heap_factor > 0.0f) || p.search.flags)
+        return fail(SEISMIC_EINVAL, "server: invalid search parameters");
+    seismic_server* sv = new (std::nothrow) seismic_server();
+    if (!sv) return fail(SEISMIC_ENOMEM, "server: host allocation failed");
+    sv->index = index;
+    sv->p = p;
+    sv->device = index->dev->device;
+    DeviceGuard g(sv->device);
+    sv->slots.resize(p.n_slots);
+    for (Slot& s : sv->slots) {
+        int rc = make_slot(sv, s);
+        if (rc) {
+            for (Slot& t : sv->slots) free_slot(t);
+            delete sv;
+            return rc;
+        }
+    }
+    sv->t0 = Clock::now();
+    try {
+        sv->worker = std::thread(run, sv);
+    } catch (...) {
+        for (Slot& t : sv->slots) free_slot(t);
+        delete sv;
+        return fail(SEISMIC_ENOMEM, "server: cannot start the dispatcher thread");
+    }
+    *out = sv;
+    return SEISMIC_OK;
+}
+
+double seismic_server_clock(const seismic_server* sv) { return sv ? sv->now() : 0.0; }
+
+int seismic_server_submit(seismic_server* sv, const uint32_t* words, uint32_t nnz, double not_before,
+                          uint64_t* ticket) {
+    if (!sv || !ticket || (nnz && !words)) return fail(SEISMIC_EINVAL, "server_submit: null argument");
+    if (nnz > SEISMIC_MAX_QUERY_NNZ) return fail(SEISMIC_EINVAL, "server_submit: %u nonzeros (max %d)", nnz, SEISMIC_MAX_QUERY_NNZ);
+    const uint32_t dim = sv->index->h.dim;
+    for (uint32_t j = 0; j < nnz; ++j) {
+        const uint32_t t = word_term(words[j]);
+        if (t >= dim || (j && t <= word_term(words[j - 1])) || !half_positive_finite(word_half(words[j])))
+            return fail(SEISMIC_EINVAL, "server_submit: invalid query entry %u", j);
+    }
+    Request r;
+    r.words.assign(words, words + nnz);
+    const double t = sv->now();
+    r.not_before = not_before;
+    r.arrival = not_before > t ? not_before : t;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->error) return fail(sv->error, "%s", sv->error_msg.c_str());
+    if (sv->stop) return fail(SEISMIC_ESTATE, "server_submit: server is stopping");
+    if (!sv->reqs.empty() && not_before < sv->reqs.back().not_before)
+        return fail(SEISMIC_EINVAL, "server_submit: not_before must not decrease between submissions");
+    *ticket = sv->reqs.size();
+    sv->reqs.push_back(std::move(r));
+    sv->cv_work.notify_one();
+    return SEISMIC_OK;
+}
+
+int seismic_server_submit_batch(seismic_server* sv, const seismic_csr* queries, const double* not_before,
+                                uint64_t* first_ticket) {
+    if (!sv || !queries || !first_ticket) return fail(SEISMIC_EINVAL, "server_submit_batch: null argument");
+    if (queries->on_device) return fail(SEISMIC_EINVAL, "server_submit_batch: queries must be host resident");
+    if (queries->dim != sv->index->h.dim) return fail(SEISMIC_EINVAL, "server_submit_batch: query dim mismatch");
+    int rc = validate_csr_host(queries, SEISMIC_MAX_QUERY_NNZ, "server_submit_batch: queries");
+    if (rc) return rc;
+    const uint64_t n = queries->n_rows;
+    for (uint64_t i = 1; i < n && not_before; ++i)
+        if (not_before[i] < not_before[i - 1]) return fail(SEISMIC_EINVAL, "server_submit_batch: not_before decreases");
+    std::deque<Request> add;
+    const double t = sv->now();
+    for (uint64_t i = 0; i < n; ++i) {
+        Request r;
+        r.words.assign(queries->words + queries->row_ptr[i], queries->words + queries->row_ptr[i + 1]);
+        r.not_before = not_before ? not_before[i] : 0.0;
+        r.arrival = r.not_before > t ? r.not_before : t;
+        add.push_back(std::move(r));
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->error) return fail(sv->error, "%s", sv->error_msg.c_str());
+    if (sv->stop) return fail(SEISMIC_ESTATE, "server_submit_batch: server is stopping");
+    if (n && !sv->reqs.empty() && add.front().not_before < sv->reqs.back().not_before)
+        return fail(SEISMIC_EINVAL, "server_submit_batch: not_before must not decrease between submissions");
+    *first_ticket = sv->reqs.size();
+    for (Request& r : add) sv->reqs.push_back(std::move(r));
+    sv->cv_work.notify_one();
+    return SEISMIC_OK;
+}
+
+int seismic_server_results(seismic_server* sv, uint64_t first_ticket, uint64_t n, uint32_t* ids, float* scores,
+                           double* latency) {
+    if (!sv) return fail(SEISMIC_EINVAL, "server_results: null server");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (first_ticket + n > sv->reqs.size()) return fail(SEISMIC_EINVAL, "server_results: unknown tickets");
+    const uint32_t k = sv->p.search.k;
+    for (uint64_t i = 0; i < n; ++i) {
+        const Request& r = sv->reqs[first_ticket + i];
+        if (!r.done) return fail(SEISMIC_ESTATE, "server_results: ticket %llu is not done", (unsigned long long)(first_ticket + i));
+        if (ids) std::memcpy(ids + i * k, r.ids.data(), k * 4);
+        if (scores) std::memcpy(scores + i * k, r.scores.data(), k * 4);
+        if (latency) latency[i] = r.done_at - r.arrival;
+    }
+    return SEISMIC_OK;
+}
+
+int seismic_server_poll(seismic_server* sv, uint64_t ticket, uint32_t* ids, float* scores, double* latency) {
+    if (!sv) return fail(SEISMIC_EINVAL, "server_poll: null server");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (ticket >= sv->reqs.size()) return fail(SEISMIC_EINVAL, "server_poll: unknown ticket");
+    const Request& r = sv->reqs[ticket];
+    if (!r.done) {
+        if (sv->error) return fail(sv->error, "%s", sv->error_msg.c_str());
+        return 0;
+    }
+    const uint32_t k = sv->p.search.k;
+    if (ids) std::memcpy(ids, r.ids.data(), k * 4);
+    if (scores) std::memcpy(scores, r.scores.data(), k * 4);
+    if (latency) *latency = r.done_at - r.arrival;
+    return 1;
+}
+
+int seismic_server_wait_all(seismic_server* sv, double timeout_s) {
+    if (!sv) return fail(SEISMIC_EINVAL, "server_wait_all: null server");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(timeout_s));
+    while (sv->completed < sv->reqs.size() && !sv->error) {
+        if (sv->cv_done.wait_until(lk, until) == std::cv_status::timeout && sv->completed < sv->reqs.size())
+            return fail(SEISMIC_ESTATE, "server_wait_all: %llu of %llu queries done after %.1f s",
+                        (unsigned long long)sv->completed, (unsigned long long)sv->reqs.size(), timeout_s);
+    }
+    if (sv->error) return fail(sv->error, "%s", sv->error_msg.c_str());
+    return SEISMIC_OK;
+}
+
+int seismic_server_stats(const seismic_server* sv, uint64_t out[4]) {
+    if (!sv || !out) return fail(SEISMIC_EINVAL, "server_stats: null argument");
+    std::lock_guard<std::mutex> lk(const_cast<seismic_server*>(sv)->mu);
+    out[0] = sv->reqs.size();
+    out[1] = sv->completed;
+    out[2] = sv->batches;
+    out[3] = sv->max_inflight;
+    return SEISMIC_OK;
+}
+
+void seismic_server_free(seismic_server* sv) {
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv_work.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    DeviceGuard g(sv->device);
+    for (Slot& s : sv->slots) free_slot(s);
+    delete sv;
+}
+
+}  // extern "C"
