@@ -243,6 +243,26 @@ int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, cons
 int exact_topk(const seismic_index* index, const seismic_csr* queries, uint32_t k, uint32_t* out_ids,
                float* out_scores, void* stream);
 
+/* ------------------------------------------------------ graph batches
+ * One search launch (the kernels seismic_search_batch enqueues for
+ * device-resident queries) captured into a HIP graph and replayed with
+ * seismic_graph_launch.  The graph is bound to the buffers given here: the
+ * queries buffer (queries->n_rows = capacity, queries->nnz = length of the
+ * words buffer), the outputs and stats, the workspace and params->probe.
+ * The batch size of each replay is read on the device from *n_queries_dev
+ * (clamped to the capacity), so one graph serves every batch written into
+ * the same buffers; row_ptr must hold n_queries + 1 valid offsets.  The
+ * launch shape is the workspace's for the capacity's bucket at capture
+ * time.  The captured work contains no memset nodes.  A workspace used by a
+ * graph must not run other searches while the graph's replays are in
+ * flight. */
+typedef struct seismic_batch_graph seismic_batch_graph;
+int seismic_graph_create(const seismic_index* index, seismic_workspace* ws, const seismic_csr* queries,
+                         const uint32_t* n_queries_dev, const seismic_search_params* params, uint32_t* out_ids,
+                         float* out_scores, const seismic_stats* stats, seismic_batch_graph** out);
+int seismic_graph_launch(seismic_batch_graph* graph, void* stream);
+void seismic_graph_free(seismic_batch_graph* graph);
+
 /* ------------------------------------------------ learned block probe
  * An addition to the method (not in the paper): training on the device.
  * All buffers are caller-owned device memory; calls are asynchronous on
@@ -318,7 +338,7 @@ typedef struct {
     uint32_t max_batch;          /* queries per batch */
     uint32_t n_slots;            /* batches in flight, 1..64 */
     uint32_t max_batch_nnz;      /* query nonzeros per batch, >= SEISMIC_MAX_QUERY_NNZ */
-    uint32_t reserved;
+    uint32_t use_graphs;         /* 1: each slot's search is a captured HIP graph (seismic_graph_create) */
     seismic_launch_config launch; /* threads = 0: the workspace default */
 } seismic_server_params;
 

@@ -62,7 +62,7 @@ class LaunchConfig(ctypes.Structure):
 
 class ServerParams(ctypes.Structure):
     _fields_ = [("search", SearchParams), ("max_batch", ctypes.c_uint32), ("n_slots", ctypes.c_uint32),
-                ("max_batch_nnz", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("launch", LaunchConfig)]
+                ("max_batch_nnz", ctypes.c_uint32), ("use_graphs", ctypes.c_uint32), ("launch", LaunchConfig)]
 
 
 class TuneResult(ctypes.Structure):
@@ -111,6 +111,9 @@ def load():
         "seismic_probe_grad": ([vp, vp, vp, vp, u32, P(ProbeLoss), vp, vp, vp, vp], i32),
         "seismic_probe_adam": ([vp, vp, vp, vp, vp, u32, P(AdamParams), vp, vp], i32),
         "seismic_server_create": ([vp, P(ServerParams), P(vp)], i32),
+        "seismic_graph_create": ([vp, vp, P(Csr), vp, P(SearchParams), vp, vp, P(Stats), P(vp)], i32),
+        "seismic_graph_launch": ([vp, vp], i32),
+        "seismic_graph_free": ([vp], None),
         "seismic_server_clock": ([vp], ctypes.c_double),
         "seismic_server_submit": ([vp, vp, u32, ctypes.c_double, P(u64)], i32),
         "seismic_server_poll": ([vp, u64, vp, vp, P(ctypes.c_double)], i32),
@@ -304,16 +307,43 @@ def seismic_probe_adam(grad_sum, stats, master, m, v, step: int, weights_out, lr
                                      ctypes.byref(ap), _ptr(weights_out), _stream_handle(stream)))
 
 
+# ------------------------------------------------------------ graph batches
+
+def seismic_graph_create(handle, ws, queries: Csr, n_queries_dev, k: int, query_cut: int, heap_factor: float,
+                         out_ids, out_scores, prefix=None, prefix_stride: int = 0, counters=None, probe=None,
+                         probe_tau: float = 0.0) -> int:
+    """Capture one search launch into a HIP graph; the batch size of each
+    replay is read from the device tensor n_queries_dev (one int32)."""
+    p = _params(k, query_cut, heap_factor, 0, probe, probe_tau)
+    st = Stats(_ptr(prefix), prefix_stride, 0, _ptr(counters), 0, 0)
+    use_stats = prefix is not None or counters is not None
+    g = ctypes.c_void_p()
+    _check(load().seismic_graph_create(handle, ws, ctypes.byref(queries), _ptr(n_queries_dev), ctypes.byref(p),
+                                       _ptr(out_ids), _ptr(out_scores), ctypes.byref(st) if use_stats else None,
+                                       ctypes.byref(g)))
+    return g.value
+
+
+def seismic_graph_launch(graph, stream=None):
+    _check(load().seismic_graph_launch(graph, _stream_handle(stream)))
+
+
+def seismic_graph_free(graph):
+    if graph:
+        load().seismic_graph_free(graph)
+
+
 # ------------------------------------------------------------ serving loop
 
 def seismic_server_create(handle, k: int, query_cut: int, heap_factor: float, max_batch: int = 1024,
                           n_slots: int = 4, max_batch_nnz: int = 0, probe=None, probe_tau: float = 0.0,
-                          launch: dict | None = None) -> int:
+                          launch: dict | None = None, use_graphs: bool = True) -> int:
     """probe (device tensor) must outlive the server."""
     sp = _params(k, query_cut, heap_factor, 0, probe, probe_tau)
     lc = LaunchConfig(0, 0, 0, 0) if not launch else LaunchConfig(launch["threads"], launch["blocks_per_cu"],
                                                                   launch["window"], 0)
-    p = ServerParams(sp, max_batch, n_slots, max_batch_nnz or max(MAX_QUERY_NNZ, 256 * max_batch), 0, lc)
+    p = ServerParams(sp, max_batch, n_slots, max_batch_nnz or max(MAX_QUERY_NNZ, 256 * max_batch),
+                     1 if use_graphs else 0, lc)
     s = ctypes.c_void_p()
     _check(load().seismic_server_create(handle, ctypes.byref(p), ctypes.byref(s)))
     return s.value

@@ -67,6 +67,11 @@ int grow(void** p, size_t& cap, size_t need, size_t elem) {
 
 constexpr int kBuckets = 4;  // batch-size buckets of the launch configuration
 
+struct seismic_batch_graph {
+    int device = -1;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct seismic_workspace {
     const seismic_index* index = nullptr;
     int device = -1;
@@ -111,8 +116,10 @@ int check_params(const seismic_index* index, const seismic_workspace* ws, const 
 // Enqueue one search of device-resident rows with launch shape cfg.
 int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64_t* q_ptr, const uint32_t* q_words,
                  uint64_t nq, uint64_t nnz, const seismic_search_params* params, uint32_t* out_ids, float* out_scores,
-                 const seismic_stats* stats, const seismic_launch_config& cfg, hipStream_t st) {
+                 const seismic_stats* stats, const seismic_launch_config& cfg, hipStream_t st,
+                 const uint32_t* nq_dev = nullptr) {
     seismic_dev::SearchArgs a{};
+    a.nq_dev = nq_dev;
     a.ix = index->dev->view;
     a.q_ptr = q_ptr;
     a.q_words = q_words;
@@ -400,6 +407,64 @@ int seismic_autotune(const seismic_index* index, seismic_workspace* ws, const se
     ws->cfg[bucket_of(queries->n_rows)] = best_cfg;
     if (n_results) *n_results = std::min(count, max_results);
     return SEISMIC_OK;
+}
+
+int seismic_graph_create(const seismic_index* index, seismic_workspace* ws, const seismic_csr* queries,
+                         const uint32_t* n_queries_dev, const seismic_search_params* params, uint32_t* out_ids,
+                         float* out_scores, const seismic_stats* stats, seismic_batch_graph** out) {
+    if (!index || !ws || !queries || !n_queries_dev || !params || !out_ids || !out_scores || !out)
+        return fail(SEISMIC_EINVAL, "graph: null argument");
+    *out = nullptr;
+    if (!queries->on_device) return fail(SEISMIC_EINVAL, "graph: queries must be device resident");
+    int rc = check_params(index, ws, queries, params);
+    if (rc) return rc;
+    if (queries->n_rows == 0) return fail(SEISMIC_EINVAL, "graph: capacity of 0 queries");
+    if (stats && stats->prefix && stats->prefix_stride < 1) return fail(SEISMIC_EINVAL, "graph: prefix_stride must be >= 1");
+    DeviceGuard g(ws->device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "graph: cannot select device");
+    seismic_batch_graph* gr = new (std::nothrow) seismic_batch_graph();
+    if (!gr) return fail(SEISMIC_ENOMEM, "graph: host allocation failed");
+    gr->device = ws->device;
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        delete gr;
+        return fail(SEISMIC_EHIP, "graph: begin capture: %s", hipGetErrorString(e));
+    }
+    rc = launch_batch(index, ws, queries->row_ptr, queries->words, queries->n_rows, queries->nnz, params, out_ids,
+                      out_scores, stats, ws->cfg[bucket_of(queries->n_rows)], cs, n_queries_dev);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (rc || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete gr;
+        return rc ? rc : fail(SEISMIC_EHIP, "graph: end capture: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        delete gr;
+        return fail(SEISMIC_EHIP, "graph: instantiate: %s", hipGetErrorString(e));
+    }
+    *out = gr;
+    return SEISMIC_OK;
+}
+
+int seismic_graph_launch(seismic_batch_graph* graph, void* stream) {
+    if (!graph) return fail(SEISMIC_EINVAL, "graph: null graph");
+    DeviceGuard g(graph->device);
+    HIP_TRY(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+    return SEISMIC_OK;
+}
+
+void seismic_graph_free(seismic_batch_graph* graph) {
+    if (!graph) return;
+    DeviceGuard g(graph->device);
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    delete graph;
 }
 
 int exact_topk(const seismic_index* index_c, const seismic_csr* queries, uint32_t k, uint32_t* out_ids,

@@ -516,12 +516,13 @@ __global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
     if (tid == 0) L.qv[0] = 0.0;
     __syncthreads();
 
+    const uint32_t nq = a.nq_dev ? min(*a.nq_dev, a.nq) : a.nq;
     for (;;) {
         // ------------------------------------------------ next query
         if (tid == 0) L.misc[15] = atomicAdd(a.queue, 1u);
         __syncthreads();
         const uint32_t qi = L.misc[15];
-        if (qi >= a.nq) break;
+        if (qi >= nq) break;
         top.which = 0;
         top.hn = 0;
 

@@ -18,7 +18,8 @@ struct SearchArgs {
     const uint64_t* q_ptr;
     const uint32_t* q_words;
     uint64_t q_nnz;     // length of q_words: row offsets are clamped to it
-    uint32_t nq;
+    uint32_t nq;        // queries (the capacity when nq_dev is set)
+    const uint32_t* nq_dev;  // optional device word holding the batch size (<= nq), read at launch
     uint32_t k;
     uint32_t cut;
     float hf;

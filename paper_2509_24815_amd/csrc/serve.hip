@@ -8,8 +8,9 @@
 // a batch is formed only when a slot is free, from the requests that have
 // arrived, in submission order, up to the slot's query and nonzero
 // capacity.  Batches on different slots overlap on the device.  A
-// dispatcher thread admits batches, launches them and delivers finished
-// results; callers submit and poll from any thread.
+// dispatcher thread admits batches, launches them (optionally as one HIP
+// graph replay per batch) and delivers finished results; callers submit and
+// poll from any thread.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -45,6 +46,9 @@ struct Slot {
     uint32_t* d_words = nullptr;
     uint32_t* d_ids = nullptr;
     float* d_scores = nullptr;
+    uint32_t* d_nq = nullptr;    // batch size read by the captured graph
+    uint32_t* h_nq = nullptr;    // pinned
+    seismic_batch_graph* graph = nullptr;
     uint64_t* h_ptr = nullptr;   // pinned
     uint32_t* h_words = nullptr; // pinned
     uint32_t* h_ids = nullptr;   // pinned
@@ -78,7 +82,10 @@ struct seismic_server {
 namespace {
 
 void free_slot(Slot& s) {
+    if (s.graph) seismic_graph_free(s.graph);
     if (s.ws) seismic_workspace_free(s.ws);
+    (void)hipFree(s.d_nq);
+    (void)hipHostFree(s.h_nq);
     (void)hipFree(s.d_ptr);
     (void)hipFree(s.d_words);
     (void)hipFree(s.d_ids);
@@ -108,6 +115,13 @@ int make_slot(seismic_server* sv, Slot& s) {
         hipHostMalloc((void**)&s.h_ids, nk * 4, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&s.h_scores, nk * 4, hipHostMallocDefault) != hipSuccess)
         return fail(SEISMIC_ENOMEM, "server: pinned host allocation of a slot failed");
+    if (p.use_graphs) {
+        if (hipMalloc((void**)&s.d_nq, 4) != hipSuccess || hipHostMalloc((void**)&s.h_nq, 4, hipHostMallocDefault) != hipSuccess)
+            return fail(SEISMIC_ENOMEM, "server: allocation of a slot failed");
+        seismic_csr q{nq, nnz, sv->index->h.dim, 1, s.d_ptr, s.d_words};
+        rc = seismic_graph_create(sv->index, s.ws, &q, s.d_nq, &p.search, s.d_ids, s.d_scores, nullptr, &s.graph);
+        if (rc) return rc;
+    }
     return SEISMIC_OK;
 }
 
@@ -116,9 +130,16 @@ int launch(seismic_server* sv, Slot& s, uint32_t nq, uint64_t nnz) {
     const uint32_t k = sv->p.search.k;
     HIP_TRY(hipMemcpyAsync(s.d_ptr, s.h_ptr, (nq + 1) * 8, hipMemcpyHostToDevice, s.stream));
     if (nnz) HIP_TRY(hipMemcpyAsync(s.d_words, s.h_words, nnz * 4, hipMemcpyHostToDevice, s.stream));
-    seismic_csr q{nq, nnz, sv->index->h.dim, 1, s.d_ptr, s.d_words};
-    int rc = seismic_search_batch(sv->index, s.ws, &q, &sv->p.search, s.d_ids, s.d_scores, nullptr, s.stream);
-    if (rc) return rc;
+    if (s.graph) {
+        *s.h_nq = nq;
+        HIP_TRY(hipMemcpyAsync(s.d_nq, s.h_nq, 4, hipMemcpyHostToDevice, s.stream));
+        int rc = seismic_graph_launch(s.graph, s.stream);
+        if (rc) return rc;
+    } else {
+        seismic_csr q{nq, nnz, sv->index->h.dim, 1, s.d_ptr, s.d_words};
+        int rc = seismic_search_batch(sv->index, s.ws, &q, &sv->p.search, s.d_ids, s.d_scores, nullptr, s.stream);
+        if (rc) return rc;
+    }
     HIP_TRY(hipMemcpyAsync(s.h_ids, s.d_ids, (size_t)nq * k * 4, hipMemcpyDeviceToHost, s.stream));
     HIP_TRY(hipMemcpyAsync(s.h_scores, s.d_scores, (size_t)nq * k * 4, hipMemcpyDeviceToHost, s.stream));
     HIP_TRY(hipEventRecord(s.event, s.stream));
