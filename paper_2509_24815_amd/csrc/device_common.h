@@ -162,7 +162,23 @@ struct TopK {
 
     // Candidates in cs/cid[0..nc), written before a barrier.  Scores <= 0
     // are not results and are ignored; ids already present are skipped.
-    __device__ void merge(uint32_t nc) {
+    __device__ void merge(uint32_t nc) { commit(merge_pending(nc)); }
+
+    // Makes the set written by merge_pending live (ns = its return value).
+    __device__ __forceinline__ void commit(uint32_t ns) {
+        if (ns) {
+            hn = min(k, hn + ns);
+            which ^= 1u;
+        }
+    }
+
+    // Smallest score of the pending set (ns > 0 and hn + ns >= k).
+    __device__ __forceinline__ float pending_min() const { return (which ? s0 : s1)[k - 1]; }
+
+    // merge() without making the result live: the merged set goes to the
+    // idle buffer; returns the number of new entries (0: nothing written,
+    // the live set is unchanged).
+    __device__ uint32_t merge_pending(uint32_t nc) {
         const int tid = threadIdx.x;
         bool ok = false;
         float s = 0.0f;
@@ -180,7 +196,7 @@ struct TopK {
         uint32_t* sd = cid + NT;
         if (ok) { ss[at] = s; sd[at] = d; }
         __syncthreads();
-        if (ns == 0) return;
+        if (ns == 0) return 0;
         const float* H = hs();
         const uint32_t* I = hid();
         float* NH = which ? s0 : s1;
@@ -200,8 +216,7 @@ struct TopK {
             if (rank < k) { NH[rank] = es; NI[rank] = ed; }
         }
         __syncthreads();
-        hn = min(k, hn + ns);
-        which ^= 1u;
+        return ns;
     }
 };
 

@@ -344,6 +344,27 @@ __device__ __noinline__ bool probe_keeps(const double* w, double tau, float r, d
     return z >= tau;
 }
 
+// The whole window (every gathered document) folded into the idle buffer of
+// the top-k without making it live; returns merge_pending's count.
+template <int NT>
+__device__ inline uint32_t fold_window_pending(const SearchLds<NT>& L, TopK<NT>& top, uint32_t tot, uint64_t& c_nnz) {
+    const int tid = threadIdx.x;
+    bool cand = false;
+    float sc = 0.0f;
+    uint32_t d = 0;
+    if ((uint32_t)tid < tot) {
+        sc = (float)L.cacc[tid];
+        d = L.cdoc[tid];
+        c_nnz += L.clen[tid];
+        cand = top.admits(sc, d);
+    }
+    uint32_t nc;
+    const uint32_t at = block_exscan<NT>(cand ? 1u : 0u, L.scratch, &nc);
+    if (cand) { top.cs[at] = sc; top.cid[at] = d; }
+    __syncthreads();
+    return nc ? top.merge_pending(nc) : 0u;
+}
+
 struct Counters {
     uint64_t sum = 0, blocks = 0, eval = 0, docs = 0, tests = 0, nnz = 0;
 };
@@ -482,7 +503,33 @@ __device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>&
             }
             __syncthreads();
             gather_and_score<NT, Look>(ix, L, look, tot, nwb, 0);
-            for (uint32_t s = 0; s < nwb; ++s) {
+            // Whole-window fold.  A probe-owned list makes no decisions.  With
+            // the heap_factor rule and a heap already full, fold everything
+            // into the idle buffer: heap.min only grows while the window is
+            // replayed, so if even the window's last (smallest r) block passes
+            // against the merged minimum, every block passes in order and the
+            // merged set is the sequential result.  Otherwise replay block by
+            // block from the unchanged live set.
+            bool folded = false;
+            if (learned) {
+                evaluated += nwb;
+                C.docs += tot;
+                fold_slot<NT>(L, top, tot, -1, C.nnz);
+                folded = true;
+            } else if (nwb > 1 && top.full() && (double)L.r[pos] * (double)a.hf >= (double)top.min_score()) {
+                uint64_t nnz = 0;
+                const uint32_t ns = fold_window_pending<NT>(L, top, tot, nnz);
+                const float m2 = ns ? top.pending_min() : top.min_score();
+                if ((double)L.r[pos + nwb - 1] * (double)a.hf >= (double)m2) {
+                    top.commit(ns);
+                    evaluated += nwb;
+                    C.tests += nwb;
+                    C.docs += tot;
+                    C.nnz += nnz;
+                    folded = true;
+                }
+            }
+            for (uint32_t s = 0; s < nwb && !folded; ++s) {
                 if (!learned && top.full()) {
                     ++C.tests;
                     if ((double)L.r[pos + s] * (double)a.hf < (double)top.min_score()) { stop = true; break; }
