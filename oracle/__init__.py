@@ -62,7 +62,7 @@ def _load():
     lib.or_exact_topk.argtypes = [vp, vp, u64, vp, vp, u64, ctypes.c_uint32, i32, vp, vp, i32]
     lib.or_exact_topk.restype = i32
     lib.or_pruned_search.argtypes = [vp, vp, vp, u64, i32, i32, f32, ctypes.c_uint32, i32, i32, vp, vp, vp, vp,
-                                     vp, f64, vp]
+                                     vp, f64, vp, vp, i32]
     lib.or_pruned_search.restype = i32
     lib.or_probe_eval.argtypes = [vp, vp, vp, vp, vp, vp, u64, vp, vp]
     lib.or_probe_eval.restype = i32
@@ -170,11 +170,12 @@ class Index:
         return "" if rc == 0 else (msg.value.decode() or "check failed")
 
     def pruned_search(self, queries, k: int, cut: int, heap_factor: float, flags: int = 0,
-                      nthreads: int = 0, c_cap: int | None = None, probe=None, tau: float = 0.0):
+                      nthreads: int = 0, c_cap: int | None = None, probe=None, tau: float = 0.0, knn=None):
         """Algorithm 2 block-pruned search.  Returns a dict with ids, scores,
         prefix (evaluated blocks per cut list), counters and hmin (smallest
         heap score at each cut list's start, -1 when the heap is not full).
-        probe: 512 bf16 weights as uint16 (learned block probe) or None."""
+        probe: 512 bf16 weights as uint16 (learned block probe) or None.
+        knn: kappa-NN graph uint32 [n_docs, kappa] (refinement) or None."""
         lib = _load()
         qrp, qw = _csr(queries)
         nq = len(qrp) - 1
@@ -191,9 +192,16 @@ class Index:
             pw = np.ascontiguousarray(probe, dtype=np.uint16)
             if pw.size != PROBE_WORDS:
                 raise ValueError(f"probe must hold {PROBE_WORDS} bf16 words")
+        kt, kappa = None, 0
+        if knn is not None:
+            kt = np.ascontiguousarray(knn, dtype=np.uint32)
+            if kt.ndim != 2 or kt.shape[0] != self.n_docs:
+                raise ValueError("knn must be uint32 [n_docs, kappa]")
+            kappa = int(kt.shape[1])
         rc = lib.or_pruned_search(self._h, _p(qrp), _p(qw), nq, k, cut, float(heap_factor), flags,
                                   nthreads or os.cpu_count() or 1, c_cap, _p(ids), _p(sc), _p(pref), _p(cnt),
-                                  None if pw is None else _p(pw), float(tau), _p(hmin))
+                                  None if pw is None else _p(pw), float(tau), _p(hmin),
+                                  None if kt is None else _p(kt), kappa)
         if rc != 0:
             raise ValueError(f"or_pruned_search failed ({rc})")
         return {"ids": ids, "scores": sc, "prefix": pref, "counters": cnt, "hmin": hmin}
@@ -247,4 +255,23 @@ def probe_quantize(x, mode: int):
     x = np.ascontiguousarray(x, dtype=np.float64)
     out = np.zeros_like(x)
     _load().or_probe_quantize(_p(x), x.size, int(mode), _p(out))
+    return out
+
+
+def knn_graph(ref: "Index", docs, kappa: int, cut: int, heap_factor: float, exact: bool = False,
+              nthreads: int = 0):
+    """kappa-NN graph (Section 4.3): for every document u, the kappa
+    documents v != u with the largest <u, v>.  exact=True uses exact search
+    (brute force); otherwise, as the paper builds it, the block-pruned
+    search with u as the query (k = kappa + 1, u itself dropped).  Rows are
+    padded with 0xFFFFFFFF."""
+    n = docs.n_rows
+    if exact:
+        ids, _ = exact_topk(docs, docs, kappa + 1, nthreads)
+    else:
+        ids = ref.pruned_search(docs, kappa + 1, cut, heap_factor, nthreads=nthreads, c_cap=max(cut, 1))["ids"]
+    out = np.full((n, kappa), 0xFFFFFFFF, dtype=np.uint32)
+    for u in range(n):
+        row = [int(v) for v in ids[u] if v != 0xFFFFFFFF and v != u][:kappa]
+        out[u, :len(row)] = row
     return out

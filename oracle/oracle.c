@@ -474,11 +474,18 @@ static float summary_score_exact(const or_index* ix, const double* qd, uint64_t 
  * the learned rule instead (see the probe section above); each of its blocks
  * counts as one prune test.  out_hmin (may be NULL) receives, per cut list,
  * the smallest heap score at the list's start (-1 when the heap is not full).
+ *
+ * kappa > 0 adds the refinement of Algorithm 2 (Section 4.5, last block)
+ * with the kappa-NN graph knn[n_docs * kappa] (0xFFFFFFFF = no neighbour):
+ * S = the ids in the heap after the traversal; every distinct neighbour of
+ * a member of S that is not itself in S is scored exactly and offered to
+ * the heap (a zero score is not a result).  Those documents are added to
+ * counters 3 and 4.
  */
 int or_pruned_search(const or_index* ix, const uint64_t* q_ptr, const uint32_t* q_words, uint64_t nq,
                      int k, int cut, float hf, uint32_t flags, int nthreads, int c_cap,
                      uint32_t* out_ids, float* out_scores, uint16_t* out_prefix, uint64_t* out_counters,
-                     const uint16_t* probe, double tau, float* out_hmin) {
+                     const uint16_t* probe, double tau, float* out_hmin, const uint32_t* knn, int kappa) {
     if (k < 1 || cut < 0 || !(hf > 0.0f) || c_cap < 1) return -1;
     double PW[OR_PROBE_WORDS];
     if (probe) probe_unpack(probe, PW);
@@ -570,6 +577,33 @@ int or_pruned_search(const or_index* ix, const uint64_t* q_ptr, const uint32_t* 
                     }
                 }
                 pref[ci] = (uint16_t)(evaluated > 65535 ? 65535 : evaluated);
+            }
+            if (kappa > 0 && knn) {
+                /* expanded set: neighbours of the heap's members, each once */
+                int ns = hn;
+                uint32_t* S = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(ns > 0 ? ns : 1));
+                uint32_t* cand = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(ns * kappa + 1));
+                for (int h = 0; h < ns; ++h) S[h] = hid[h];
+                int nc = 0;
+                for (int h = 0; h < ns; ++h)
+                    for (int j = 0; j < kappa; ++j) {
+                        uint32_t v = knn[(size_t)S[h] * kappa + j];
+                        if (v == 0xFFFFFFFFu || v >= ix->n_docs) continue;
+                        int seen = 0;
+                        for (int x = 0; x < ns && !seen; ++x) seen = S[x] == v;
+                        for (int x = 0; x < nc && !seen; ++x) seen = cand[x] == v;
+                        if (!seen) cand[nc++] = v;
+                    }
+                for (int c = 0; c < nc; ++c) {
+                    uint32_t d = cand[c];
+                    uint64_t r0 = ix->row_ptr[d], r1 = ix->row_ptr[d + 1];
+                    cnt[3]++;
+                    cnt[4] += r1 - r0;
+                    float sc = dot_exact(qd, ix->words + r0, r1 - r0);
+                    if (sc > 0.0f) topk_insert(hs, hid, &hn, k, sc, d);
+                }
+                free(S);
+                free(cand);
             }
             emit(out_scores + (size_t)qi * k, out_ids + (size_t)qi * k, hs, hid, hn, k);
             for (int j = 0; j < nqe; ++j) qd[qe[j].term] = 0.0;
