@@ -97,10 +97,18 @@ typedef struct {
     uint32_t k;
     uint32_t query_cut;
     float heap_factor;
-    uint32_t flags; /* must be 0 */
+    uint32_t flags; /* 0 or SEISMIC_SEARCH_KNN */
     const uint16_t* probe;
     double probe_tau;
 } seismic_search_params;
+
+/* flags: refine with the index's kappa-NN graph (Algorithm 2, last block;
+   Section 4.3): after the traversal, S = the ids in the heap; every distinct
+   neighbour of a member of S that is not in S is scored exactly and offered
+   to the heap (zero scores are not results; the documents count in
+   counters 3 and 4).  Needs a graph (seismic_knn_build or
+   seismic_index_set_knn: ESTATE otherwise) and k * kappa <= 256 (EINVAL). */
+#define SEISMIC_SEARCH_KNN 1u
 
 #define SEISMIC_PROBE_WORDS 512 /* W1[64][5] (row = hidden unit), b1[64], w2[64], b2, zero padding */
 
@@ -225,7 +233,7 @@ int seismic_autotune(const seismic_index* index, seismic_workspace* ws, const se
  * and copied through the workspace; device-resident queries are checked by
  * the kernel, which never reads out of bounds and reports a per-query
  * status in stats->counters.  EINVAL: bad parameters (k = 0 or > max_k,
- * heap_factor <= 0 or NaN, flags != 0, batch larger than the workspace).
+ * heap_factor <= 0 or NaN, unknown flags, batch larger than the workspace).
  */
 int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, const seismic_csr* queries,
                          const seismic_search_params* params, uint32_t* out_ids, float* out_scores,
@@ -242,6 +250,22 @@ int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, cons
  */
 int exact_topk(const seismic_index* index, const seismic_csr* queries, uint32_t k, uint32_t* out_ids,
                float* out_scores, void* stream);
+
+/* ------------------------------------------------------- kappa-NN graph
+ * The graph of Section 4.3: N(u) = the kappa documents v != u with the
+ * largest <u, v> (ties by id), 0xFFFFFFFF padding; table [n_docs * kappa]
+ * u32, row u = N(u).  Kept on the index's device; 1 <= kappa <= 256. */
+
+/* Approximate graph built as the paper does, with the method itself: every
+ * document searched as a query (block-pruned search, k = kappa + 1,
+ * query_cut, heap_factor) against the resident index, itself dropped.
+ * Synchronous; replaces any previous graph. */
+int seismic_knn_build(seismic_index* index, uint32_t kappa, uint32_t query_cut, float heap_factor);
+/* Install a graph from host (on_device = 0) or device memory (copied). */
+int seismic_index_set_knn(seismic_index* index, uint32_t kappa, const uint32_t* table, uint32_t on_device);
+/* *kappa = the graph's kappa (0: none); out_host (nullable) receives the
+ * table. */
+int seismic_index_get_knn(const seismic_index* index, uint32_t* out_host, uint32_t* kappa);
 
 /* ------------------------------------------------------ graph batches
  * One search launch (the kernels seismic_search_batch enqueues for

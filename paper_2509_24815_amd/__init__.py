@@ -49,7 +49,7 @@ class Index:
 
     def search(self, queries, k: int, query_cut: int, heap_factor: float, *, stats: bool = False,
                prefix_stride: int | None = None, stream=None, ws=None, probe=None, probe_tau: float = 0.0,
-               trace: bool = False):
+               trace: bool = False, refine: bool = False):
         """Batched search.  ``queries`` is a binding.Csr (host or device).
         Returns torch tensors on the current device (ids, scores[, prefix,
         counters[, list_hmin, list_term]]).  probe: device tensor of
@@ -73,12 +73,23 @@ class Index:
         w = ws if ws is not None else self.workspace(max(nq, 1), max(k, 1))
         binding.seismic_search_batch(self.handle, w, queries, k, query_cut, heap_factor, ids, sc,
                                      prefix, stride, counters, stream, probe=probe, probe_tau=probe_tau,
-                                     list_hmin=hmin, list_term=term)
+                                     list_hmin=hmin, list_term=term,
+                                     flags=binding.SEARCH_KNN if refine else 0)
         if trace:
             return ids, sc, prefix, counters, hmin, term
         if stats:
             return ids, sc, prefix, counters
         return ids, sc
+
+    def build_knn(self, kappa: int, query_cut: int = 10, heap_factor: float = 0.8):
+        """kappa-NN graph by searching every document (GPU)."""
+        binding.seismic_knn_build(self.handle, kappa, query_cut, heap_factor)
+
+    def set_knn(self, table):
+        binding.seismic_index_set_knn(self.handle, table)
+
+    def knn(self):
+        return binding.seismic_index_get_knn(self.handle, self.info()["n_docs"])
 
     def exact(self, queries, k: int, stream=None):
         import torch

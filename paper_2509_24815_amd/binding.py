@@ -75,6 +75,7 @@ class Stats(ctypes.Structure):
 
 
 PROBE_WORDS = 512
+SEARCH_KNN = 1  # seismic_search_params.flags: kappa-NN refinement
 
 
 def load():
@@ -111,6 +112,9 @@ def load():
         "seismic_probe_grad": ([vp, vp, vp, vp, u32, P(ProbeLoss), vp, vp, vp, vp], i32),
         "seismic_probe_adam": ([vp, vp, vp, vp, vp, u32, P(AdamParams), vp, vp], i32),
         "seismic_server_create": ([vp, P(ServerParams), P(vp)], i32),
+        "seismic_knn_build": ([vp, u32, u32, ctypes.c_float], i32),
+        "seismic_index_set_knn": ([vp, u32, vp, u32], i32),
+        "seismic_index_get_knn": ([vp, vp, P(u32)], i32),
         "seismic_graph_create": ([vp, vp, P(Csr), vp, P(SearchParams), vp, vp, P(Stats), P(vp)], i32),
         "seismic_graph_launch": ([vp, vp], i32),
         "seismic_graph_free": ([vp], None),
@@ -305,6 +309,34 @@ def seismic_probe_adam(grad_sum, stats, master, m, v, step: int, weights_out, lr
     ap = AdamParams(lr, beta1, beta2, eps)
     _check(load().seismic_probe_adam(_ptr(grad_sum), _ptr(stats), _ptr(master), _ptr(m), _ptr(v), step,
                                      ctypes.byref(ap), _ptr(weights_out), _stream_handle(stream)))
+
+
+# ----------------------------------------------------------- kappa-NN graph
+
+def seismic_knn_build(handle, kappa: int, query_cut: int, heap_factor: float):
+    _check(load().seismic_knn_build(handle, kappa, query_cut, heap_factor))
+
+
+def seismic_index_set_knn(handle, table):
+    """table: uint32 numpy [n_docs, kappa] (host) or an int32 torch tensor on
+    the device."""
+    if hasattr(table, "data_ptr"):
+        kappa, dev = int(table.shape[1]), 1
+    else:
+        table = np.ascontiguousarray(table, dtype=np.uint32)
+        kappa, dev = int(table.shape[1]), 0
+    _check(load().seismic_index_set_knn(handle, kappa, _ptr(table), dev))
+
+
+def seismic_index_get_knn(handle, n_docs: int):
+    """The index's graph as uint32 [n_docs, kappa], or None."""
+    kap = ctypes.c_uint32(0)
+    _check(load().seismic_index_get_knn(handle, None, ctypes.byref(kap)))
+    if kap.value == 0:
+        return None
+    out = np.empty((n_docs, kap.value), dtype=np.uint32)
+    _check(load().seismic_index_get_knn(handle, _ptr(out), ctypes.byref(kap)))
+    return out
 
 
 # ------------------------------------------------------------ graph batches

@@ -24,6 +24,7 @@ void device_index_free(DeviceIndex* d) {
     (void)hipFree(d->csc_val);
     (void)hipFree(d->xq_ptr);
     (void)hipFree(d->xq_words);
+    (void)hipFree(d->knn);
     if (switched) (void)hipSetDevice(prev);
     delete d;
 }
@@ -66,6 +67,7 @@ int grow(void** p, size_t& cap, size_t need, size_t elem) {
 }
 
 constexpr int kBuckets = 4;  // batch-size buckets of the launch configuration
+constexpr uint32_t kMaxRefine = 256;  // refinement candidates per query (k * kappa), one workgroup pass
 
 struct seismic_batch_graph {
     int device = -1;
@@ -105,7 +107,13 @@ int check_params(const seismic_index* index, const seismic_workspace* ws, const 
     if (ws->index != index) return fail(SEISMIC_EINVAL, "search: workspace belongs to another index");
     if (params->k < 1 || params->k > ws->max_k) return fail(SEISMIC_EINVAL, "search: k = %u outside [1, %u]", params->k, ws->max_k);
     if (!(params->heap_factor > 0.0f)) return fail(SEISMIC_EINVAL, "search: heap_factor must be > 0");
-    if (params->flags != 0) return fail(SEISMIC_EINVAL, "search: unknown flags");
+    if (params->flags & ~SEISMIC_SEARCH_KNN) return fail(SEISMIC_EINVAL, "search: unknown flags");
+    if (params->flags & SEISMIC_SEARCH_KNN) {
+        if (!index->dev->knn) return fail(SEISMIC_ESTATE, "search: the index has no kappa-NN graph");
+        if ((uint64_t)params->k * index->dev->kappa > kMaxRefine)
+            return fail(SEISMIC_EINVAL, "search: refinement needs k * kappa <= %u (k %u, kappa %u)", kMaxRefine,
+                        params->k, index->dev->kappa);
+    }
     if (params->probe && !(params->probe_tau == params->probe_tau)) return fail(SEISMIC_EINVAL, "search: probe_tau is NaN");
     if (queries->dim != index->h.dim) return fail(SEISMIC_EINVAL, "search: query dim %u != index dim %u", queries->dim, index->h.dim);
     if (queries->n_rows > ws->max_queries)
@@ -151,6 +159,22 @@ int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64
     if (cfg.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)cfg.blocks_per_cu);
     uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ws->n_cu, nq);
     HIP_TRY(seismic_dev::launch_search(a, nt, grid, smem, st));
+    if (params->flags & SEISMIC_SEARCH_KNN) {
+        seismic_dev::RefineArgs r{};
+        r.ix = a.ix;
+        r.q_ptr = q_ptr;
+        r.q_words = q_words;
+        r.q_nnz = nnz;
+        r.nq = a.nq;
+        r.nq_dev = nq_dev;
+        r.k = params->k;
+        r.knn = index->dev->knn;
+        r.kappa = index->dev->kappa;
+        r.ids = out_ids;
+        r.scores = out_scores;
+        r.counters = a.counters;
+        HIP_TRY(seismic_dev::launch_refine(r, st));
+    }
     return SEISMIC_OK;
 }
 
@@ -465,6 +489,108 @@ void seismic_graph_free(seismic_batch_graph* graph) {
     DeviceGuard g(graph->device);
     if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
     delete graph;
+}
+
+int seismic_index_set_knn(seismic_index* index, uint32_t kappa, const uint32_t* table, uint32_t on_device) {
+    if (!index || !table) return fail(SEISMIC_EINVAL, "set_knn: null argument");
+    if (!index->dev) return fail(SEISMIC_ESTATE, "set_knn: index is not on a device");
+    if (kappa < 1 || kappa > kMaxRefine) return fail(SEISMIC_EINVAL, "set_knn: kappa must be in [1, %u]", kMaxRefine);
+    DeviceIndex* d = index->dev;
+    DeviceGuard g(d->device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "set_knn: cannot select device");
+    std::lock_guard<std::mutex> lk(index->mu);
+    const size_t bytes = std::max<size_t>((size_t)index->h.n_docs * kappa * 4, 16);
+    uint32_t* t = nullptr;
+    if (hipMalloc((void**)&t, bytes) != hipSuccess) return fail(SEISMIC_ENOMEM, "set_knn: %zu bytes of device memory", bytes);
+    hipError_t e = hipMemcpy(t, table, (size_t)index->h.n_docs * kappa * 4,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(t);
+        return fail(SEISMIC_EHIP, "set_knn: copy failed: %s", hipGetErrorString(e));
+    }
+    (void)hipFree(d->knn);
+    d->knn = t;
+    d->kappa = kappa;
+    return SEISMIC_OK;
+}
+
+int seismic_index_get_knn(const seismic_index* index, uint32_t* out_host, uint32_t* kappa) {
+    if (!index || !kappa) return fail(SEISMIC_EINVAL, "get_knn: null argument");
+    *kappa = 0;
+    if (!index->dev || !index->dev->knn) return SEISMIC_OK;
+    *kappa = index->dev->kappa;
+    if (!out_host) return SEISMIC_OK;
+    DeviceGuard g(index->dev->device);
+    HIP_TRY(hipMemcpy(out_host, index->dev->knn, (size_t)index->h.n_docs * index->dev->kappa * 4, hipMemcpyDeviceToHost));
+    return SEISMIC_OK;
+}
+
+// Row u of the graph from the search of document u: its first kappa
+// results other than u (0xFFFFFFFF padding kept).
+__global__ void k_knn_finalize(const uint32_t* __restrict__ ids, uint32_t n, uint32_t first, uint32_t kappa,
+                               uint32_t* __restrict__ table) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t u = first + i;
+    const uint32_t* row = ids + (size_t)i * (kappa + 1);
+    uint32_t* out = table + (size_t)u * kappa;
+    uint32_t w = 0;
+    for (uint32_t j = 0; j <= kappa && w < kappa; ++j)
+        if (row[j] != u && row[j] != 0xFFFFFFFFu) out[w++] = row[j];
+    for (; w < kappa; ++w) out[w] = 0xFFFFFFFFu;
+}
+
+int seismic_knn_build(seismic_index* index, uint32_t kappa, uint32_t query_cut, float heap_factor) {
+    if (!index) return fail(SEISMIC_EINVAL, "knn_build: null index");
+    if (!index->dev) return fail(SEISMIC_ESTATE, "knn_build: index is not on a device");
+    if (kappa < 1 || kappa > kMaxRefine) return fail(SEISMIC_EINVAL, "knn_build: kappa must be in [1, %u]", kMaxRefine);
+    if (!(heap_factor > 0.0f)) return fail(SEISMIC_EINVAL, "knn_build: heap_factor must be > 0");
+    DeviceIndex* d = index->dev;
+    DeviceGuard g(d->device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "knn_build: cannot select device");
+    const uint64_t n = index->h.n_docs;
+    const uint32_t chunk = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(n, 1), 65536);
+    seismic_workspace* ws = nullptr;
+    int rc = seismic_workspace_create(index, chunk, kappa + 1, &ws);
+    if (rc) return rc;
+    uint32_t *table = nullptr, *ids = nullptr;
+    float* sc = nullptr;
+    const size_t tbytes = std::max<size_t>((size_t)n * kappa * 4, 16);
+    if (hipMalloc((void**)&table, tbytes) != hipSuccess ||
+        hipMalloc((void**)&ids, (size_t)chunk * (kappa + 1) * 4) != hipSuccess ||
+        hipMalloc((void**)&sc, (size_t)chunk * (kappa + 1) * 4) != hipSuccess) {
+        (void)hipFree(table); (void)hipFree(ids);
+        seismic_workspace_free(ws);
+        return fail(SEISMIC_ENOMEM, "knn_build: device allocation failed");
+    }
+    seismic_search_params sp{};
+    sp.k = kappa + 1;
+    sp.query_cut = query_cut;
+    sp.heap_factor = heap_factor;
+    for (uint64_t s = 0; s < n && !rc; s += chunk) {
+        const uint32_t m = (uint32_t)std::min<uint64_t>(chunk, n - s);
+        // documents [s, s + m) of the resident forward index as the queries
+        seismic_csr q{m, index->h.nnz(), index->h.dim, 1, d->view.row_ptr + s, d->view.words};
+        rc = seismic_search_batch(index, ws, &q, &sp, ids, sc, nullptr, nullptr);
+        if (!rc) {
+            hipLaunchKernelGGL(k_knn_finalize, dim3((m + 255) / 256), dim3(256), 0, nullptr, ids, m, (uint32_t)s, kappa,
+                               table);
+            if (hipGetLastError() != hipSuccess) rc = fail(SEISMIC_EHIP, "knn_build: finalize launch failed");
+        }
+    }
+    if (!rc && hipDeviceSynchronize() != hipSuccess) rc = fail(SEISMIC_EHIP, "knn_build: synchronize failed");
+    (void)hipFree(ids);
+    (void)hipFree(sc);
+    seismic_workspace_free(ws);
+    if (rc) {
+        (void)hipFree(table);
+        return rc;
+    }
+    std::lock_guard<std::mutex> lk(index->mu);
+    (void)hipFree(d->knn);
+    d->knn = table;
+    d->kappa = kappa;
+    return SEISMIC_OK;
 }
 
 int exact_topk(const seismic_index* index_c, const seismic_csr* queries, uint32_t k, uint32_t* out_ids,

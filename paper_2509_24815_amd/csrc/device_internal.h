@@ -29,6 +29,9 @@ struct DeviceIndex {
     uint64_t* xq_ptr = nullptr;
     uint32_t* xq_words = nullptr;
     size_t xq_rows_cap = 0, xq_words_cap = 0;
+    // kappa-NN graph [n_docs * kappa] (optional)
+    uint32_t* knn = nullptr;
+    uint32_t kappa = 0;
 };
 
 // Makes a device current for the lifetime of the object.

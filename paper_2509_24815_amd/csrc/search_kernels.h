@@ -57,6 +57,26 @@ struct ExactArgs {
     float* out_scores;
 };
 
+// Refinement with the kappa-NN graph, one workgroup per query, run after
+// the search on its results (ids/scores rows of k, updated in place).
+struct RefineArgs {
+    DevIdx ix;
+    const uint64_t* q_ptr;
+    const uint32_t* q_words;
+    uint64_t q_nnz;
+    uint32_t nq;
+    const uint32_t* nq_dev;  // optional device batch size (<= nq)
+    uint32_t k;
+    const uint32_t* knn;     // [n_docs * kappa]
+    uint32_t kappa;          // k * kappa <= kRefineThreads
+    uint32_t* ids;
+    float* scores;
+    uint64_t* counters;      // optional [nq * 8]: documents and nonzeros added to entries 3 and 4
+};
+
+constexpr uint32_t kRefineThreads = 256;
+hipError_t launch_refine(const RefineArgs& a, hipStream_t stream);
+
 size_t exact_smem_bytes(uint32_t k);
 hipError_t launch_exact(const ExactArgs& a, uint32_t nq, size_t smem, hipStream_t stream);
 

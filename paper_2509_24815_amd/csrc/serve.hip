@@ -250,7 +250,8 @@ int seismic_server_create(const seismic_index* index, const seismic_server_param
     if (p.max_batch < 1) return fail(SEISMIC_EINVAL, "server: max_batch must be >= 1");
     if (p.max_batch_nnz < SEISMIC_MAX_QUERY_NNZ)
         return fail(SEISMIC_EINVAL, "server: max_batch_nnz must be >= %d", SEISMIC_MAX_QUERY_NNZ);
-    if (p.search.k < 1 || p.search.k > SEISMIC_MAX_K || !(p.search.heap_factor > 0.0f) || p.search.flags)
+    if (p.search.k < 1 || p.search.k > SEISMIC_MAX_K || !(p.search.heap_factor > 0.0f) ||
+        (p.search.flags & ~SEISMIC_SEARCH_KNN))
         return fail(SEISMIC_EINVAL, "server: invalid search parameters");
     seismic_server* sv = new (std::nothrow) seismic_server();
     if (!sv) return fail(SEISMIC_ENOMEM, "server: host allocation failed");
