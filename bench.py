@@ -134,7 +134,11 @@ def main():
     ap.add_argument("--index-cache", default=None, help="load the index from this file if present, else build and save")
     ap.add_argument("--plain-rows", action="store_true", help="search the forward rows in place (no block-major copies)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--grid", default="", help="also sweep query_cut x heap_factor, e.g. '5,10,20x0.7,0.8,0.9'")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--knn", type=int, default=20, help="kappa of the kappa-NN graph for the refined form (0 = skip)")
+    ap.add_argument("--knn-cut", type=int, default=10, help="query_cut of the graph-building searches")
+    ap.add_argument("--knn-hf", type=float, default=0.5, help="heap_factor of the graph-building searches")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per serving rate")
     ap.add_argument("--probe", default=os.path.join(ROOT, "paper_2509_24815_amd", "probes", "probe_1m.npy"),
                     help="learned block-probe weights to evaluate beside the heap_factor rule ('' = skip)")
@@ -204,7 +208,8 @@ def main():
     out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     out_sc = torch.empty((nq, k), dtype=torch.float32, device=dev)
     cut = W["cut"]
-    prefix = torch.zeros((nq, cut), dtype=torch.int16, device=dev)
+    grid_cuts = sorted({int(c) for c in args.grid.split("x")[0].split(",")}) if args.grid else []
+    prefix = torch.zeros((nq, max([cut] + grid_cuts)), dtype=torch.int16, device=dev)
     counters = torch.zeros((nq, 8), dtype=torch.int64, device=dev)
 
     # ground truth
@@ -230,23 +235,28 @@ def main():
             tie.append(min(n, int((asc[a != 0xFFFFFFFF] >= kth).sum())) / n)
         return float(np.mean(strict)), float(np.mean(tie))
 
-    def run(hf, with_stats, probe=None, tau=0.0):
-        binding.seismic_search_batch(ix.handle, ws, qcsr, k, cut, hf, out_ids, out_sc,
-                                     prefix if with_stats else None, cut if with_stats else 0,
-                                     counters if with_stats else None, stream, probe=probe, probe_tau=tau)
+    def run(hf, with_stats, probe=None, tau=0.0, c=None, flags=0):
+        c = c or cut
+        binding.seismic_search_batch(ix.handle, ws, qcsr, k, c, hf, out_ids, out_sc,
+                                     prefix if with_stats else None, c if with_stats else 0,
+                                     counters if with_stats else None, stream, probe=probe, probe_tau=tau,
+                                     flags=flags)
 
-    def measure(hf, probe=None, tau=0.0):
-        run(hf, True, probe, tau)
+    def measure(hf, probe=None, tau=0.0, c=None, flags=0):
+        run(hf, True, probe, tau, c, flags)
         torch.cuda.synchronize()
-        ts = time.time()
-        for _ in range(2):
-            run(hf, False, probe, tau)
-        torch.cuda.synchronize()
-        dt = (time.time() - ts) / 2
-        rs, rt = recall_of(out_ids.cpu().numpy().view(np.uint32), out_sc.cpu().numpy())
         cnt = counters.cpu().numpy()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(2):
+            run(hf, False, probe, tau, c, flags)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        dt = ev[0].elapsed_time(ev[1]) / 2e3
+        rs, rt = recall_of(out_ids.cpu().numpy().view(np.uint32), out_sc.cpu().numpy())
         return dict(recall=round(rs, 4), recall_tie_aware=round(rt, 4), qps=round(nq / dt, 1),
-                    docs_evaluated=float(cnt[:, 3].mean()), blocks_evaluated=float(cnt[:, 2].mean()))
+                    docs_evaluated=float(cnt[:, 3].mean()), blocks_evaluated=float(cnt[:, 2].mean()),
+                    alg_gbs=round(float(alg_bytes(cnt, q_nnz, k).sum()) / dt / 1e9, 1))
 
     def search_grid(values, key, fn):
         """Walk values from most to least pruning; stop at the first point
@@ -318,6 +328,18 @@ def main():
 
     plain_ids = out_ids.cpu().numpy().view(np.uint32).copy()  # results of the timed steps
 
+    # query_cut x heap_factor grid (same batch, autotuned shape)
+    grid = None
+    if args.grid:
+        hf_list = [float(x) for x in args.grid.split("x")[1].split(",")]
+        grid = []
+        for c in grid_cuts:
+            for hf in hf_list:
+                pt = dict(query_cut=c, hf=hf, **measure(hf, c=c))
+                pt["alg_frac"] = round(pt["alg_gbs"] / PEAK_HBM_GBS, 4)
+                grid.append(pt)
+                log(f"[bench] grid {pt}")
+
     # learned block probe (lists that start with a full heap), heap_factor rule elsewhere
     learned = None
     if args.probe and os.path.exists(args.probe):
@@ -338,13 +360,55 @@ def main():
             torch.cuda.synchronize()
             lms = l0.elapsed_time(l1) / args.steps
             learned = {"probe": os.path.relpath(args.probe, ROOT), "tau": tau, "heap_factor_fallback": chosen,
-                       "recall_at_10": lp["recall"], "qps": round(nq / (lms / 1e3), 1), "ms_per_step": round(lms, 4),
+                       f"recall_at_{k}": lp["recall"], "qps": round(nq / (lms / 1e3), 1), "ms_per_step": round(lms, 4),
                        "docs_evaluated": lp["docs_evaluated"], "qps_vs_heap_factor_rule": round(lms and ms_per_step / lms, 4),
                        "docs_vs_heap_factor_rule": round(lp["docs_evaluated"] / point["docs_evaluated"], 4),
                        "sweep": lpts}
         else:
             learned = {"probe": os.path.relpath(args.probe, ROOT), "reached_target": False, "sweep": lpts}
         log(f"[bench] learned probe {learned}")
+
+    # refined form: kappa-NN graph built on the GPU with the method itself,
+    # then the refinement step after every search
+    refined = None
+    if args.knn > 0 and k * args.knn <= 256:
+        tb = time.time()
+        binding.seismic_knn_build(ix.handle, args.knn, args.knn_cut, args.knn_hf)
+        knn_s = time.time() - tb
+        log(f"[bench] kappa-NN graph (kappa {args.knn}, cut {args.knn_cut}, hf {args.knn_hf}) built in {knn_s:.1f} s")
+        best = None
+        rpts = []
+        for c in sorted({max(1, cut // 2), cut}):
+            ch, pts = search_grid([0.1, 0.2] + list(W["hfs"]), "hf",
+                                  lambda h: measure(h, c=c, flags=binding.SEARCH_KNN))
+            for p_ in pts:
+                p_["query_cut"] = c
+            rpts += pts
+            if ch is not None:
+                pt = next(p_ for p_ in pts if p_["hf"] == ch)
+                if best is None or pt["qps"] > best["qps"]:
+                    best = pt
+        if best is not None:
+            c, h = best["query_cut"], best["hf"]
+            for _ in range(args.warmup):
+                run(h, False, c=c, flags=binding.SEARCH_KNN)
+            torch.cuda.synchronize()
+            r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            r0.record(stream)
+            for _ in range(args.steps):
+                run(h, False, c=c, flags=binding.SEARCH_KNN)
+            r1.record(stream)
+            torch.cuda.synchronize()
+            rms = r0.elapsed_time(r1) / args.steps
+            refined = {"kappa": args.knn, "graph_build_s": round(knn_s, 1),
+                       "graph_search": {"query_cut": args.knn_cut, "heap_factor": args.knn_hf},
+                       "query_cut": c, "heap_factor": h, f"recall_at_{k}": best["recall"],
+                       "qps": round(nq / (rms / 1e3), 1), "ms_per_step": round(rms, 4),
+                       "docs_evaluated": best["docs_evaluated"],
+                       "qps_vs_heap_factor_rule": round(ms_per_step / rms, 4), "sweep": rpts}
+        else:
+            refined = {"kappa": args.knn, "graph_build_s": round(knn_s, 1), "reached_target": False, "sweep": rpts}
+        log(f"[bench] refined {refined}")
 
     # serving loop: Poisson arrivals, continuous batching over 4 slots
     serving = None
@@ -390,9 +454,15 @@ def main():
         cpu_s = time.time() - tc
         g_ids = plain_ids[:n_sample]
         match = float((r["ids"] == g_ids).all(axis=1).mean())
+        # the paper's protocol: one thread, mean latency per query
+        one = qs.subset(range(min(nq, max(8, int(3.0 / max(per_q * threads, 1e-9))))))
+        t1 = time.time()
+        ref.pruned_search(one, k, cut, chosen, nthreads=1, c_cap=cut)
+        st_ms = (time.time() - t1) / one.n_rows * 1e3
         cpu = {"value": round(n_sample / cpu_s, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
                "sample": f"first {n_sample} of the {nq} queries, heap_factor {chosen}, {cpu_s:.1f} s",
-               "gpu_match_fraction": match}
+               "gpu_match_fraction": match, "single_thread_ms_per_query": round(st_ms, 3),
+               "single_thread_sample": one.n_rows}
         log(f"[bench] CPU baseline {cpu}")
         del ref, buf
 
@@ -413,10 +483,10 @@ def main():
         "config": {"workload": f"{args.workload}: {W['n_docs']} docs, {nq}-query batch ({W['qlaw']} nnz), "
                                f"lambda {W['lam']}, beta {W['beta']}, gamma {W['gamma']}, query_cut {cut}, "
                                f"k {k}, heap_factor {chosen}",
-                   "recall_at_10": point["recall"], "recall_target": args.recall,
+                   f"recall_at_{k}": point["recall"], "recall_target": args.recall,
                    "index_build_s": None if build_s is None else round(build_s, 1),
                    "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
-                   "sweep": sweep, "learned_probe": learned},
+                   "sweep": sweep, "learned_probe": learned, "knn_refined": refined, "grid": grid},
         "serving": serving,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
