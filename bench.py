@@ -408,6 +408,27 @@ def main():
                        "qps_vs_heap_factor_rule": round(ms_per_step / rms, 4), "sweep": rpts}
         else:
             refined = {"kappa": args.knn, "graph_build_s": round(knn_s, 1), "reached_target": False, "sweep": rpts}
+        # both additions together: learned probe for the traversal, then refinement
+        if learned and learned.get("tau") is not None:
+            taus = [2.0, 1.5, 1.0, 0.75, 0.5, 0.25, 0.0, -0.25, -0.5, -1.0]
+            t2, lpts2 = search_grid(taus, "tau", lambda t: measure(chosen, pw, t, flags=binding.SEARCH_KNN))
+            both = {"tau": t2, "heap_factor_fallback": chosen, "sweep": lpts2}
+            if t2 is not None:
+                lp2 = next(p_ for p_ in lpts2 if p_["tau"] == t2)
+                for _ in range(args.warmup):
+                    run(chosen, False, pw, t2, flags=binding.SEARCH_KNN)
+                torch.cuda.synchronize()
+                b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                b0.record(stream)
+                for _ in range(args.steps):
+                    run(chosen, False, pw, t2, flags=binding.SEARCH_KNN)
+                b1.record(stream)
+                torch.cuda.synchronize()
+                bms = b0.elapsed_time(b1) / args.steps
+                both.update({f"recall_at_{k}": lp2["recall"], "qps": round(nq / (bms / 1e3), 1),
+                             "ms_per_step": round(bms, 4), "docs_evaluated": lp2["docs_evaluated"],
+                             "qps_vs_heap_factor_rule": round(ms_per_step / bms, 4)})
+            refined["with_learned_probe"] = both
         log(f"[bench] refined {refined}")
 
     # serving loop: Poisson arrivals, continuous batching over 4 slots
