@@ -62,7 +62,7 @@ def _load():
     lib.or_exact_topk.argtypes = [vp, vp, u64, vp, vp, u64, ctypes.c_uint32, i32, vp, vp, i32]
     lib.or_exact_topk.restype = i32
     lib.or_pruned_search.argtypes = [vp, vp, vp, u64, i32, i32, f32, ctypes.c_uint32, i32, i32, vp, vp, vp, vp,
-                                     vp, f64, vp, vp, i32]
+                                     vp, f64, vp, vp, i32, f64]
     lib.or_pruned_search.restype = i32
     lib.or_probe_eval.argtypes = [vp, vp, vp, vp, vp, vp, u64, vp, vp]
     lib.or_probe_eval.restype = i32
@@ -170,12 +170,14 @@ class Index:
         return "" if rc == 0 else (msg.value.decode() or "check failed")
 
     def pruned_search(self, queries, k: int, cut: int, heap_factor: float, flags: int = 0,
-                      nthreads: int = 0, c_cap: int | None = None, probe=None, tau: float = 0.0, knn=None):
+                      nthreads: int = 0, c_cap: int | None = None, probe=None, tau: float = 0.0, knn=None,
+                      query_mass: float = 0.0):
         """Algorithm 2 block-pruned search.  Returns a dict with ids, scores,
         prefix (evaluated blocks per cut list), counters and hmin (smallest
         heap score at each cut list's start, -1 when the heap is not full).
         probe: 512 bf16 weights as uint16 (learned block probe) or None.
-        knn: kappa-NN graph uint32 [n_docs, kappa] (refinement) or None."""
+        knn: kappa-NN graph uint32 [n_docs, kappa] (refinement) or None.
+        query_mass: alpha_q of the query's alpha_q-MSS cut (0 = fixed cut)."""
         lib = _load()
         qrp, qw = _csr(queries)
         nq = len(qrp) - 1
@@ -201,7 +203,7 @@ class Index:
         rc = lib.or_pruned_search(self._h, _p(qrp), _p(qw), nq, k, cut, float(heap_factor), flags,
                                   nthreads or os.cpu_count() or 1, c_cap, _p(ids), _p(sc), _p(pref), _p(cnt),
                                   None if pw is None else _p(pw), float(tau), _p(hmin),
-                                  None if kt is None else _p(kt), kappa)
+                                  None if kt is None else _p(kt), kappa, float(query_mass))
         if rc != 0:
             raise ValueError(f"or_pruned_search failed ({rc})")
         return {"ids": ids, "scores": sc, "prefix": pref, "counters": cnt, "hmin": hmin}

@@ -475,6 +475,12 @@ static float summary_score_exact(const or_index* ix, const double* qd, uint64_t 
  * counts as one prune test.  out_hmin (may be NULL) receives, per cut list,
  * the smallest heap score at the list's start (-1 when the heap is not full).
  *
+ * qmass > 0 shortens the cut to the alpha_q-MSS of the query (Definition
+ * of alpha-MSS, Section 3.2, with alpha_q = qmass; ties by term id): the
+ * first m entries of the cut order, m the smallest count whose values sum
+ * to at least qmass times the query's l1 mass (fp64, exact); cut > 0 still
+ * caps the count.
+ *
  * kappa > 0 adds the refinement of Algorithm 2 (Section 4.5, last block)
  * with the kappa-NN graph knn[n_docs * kappa] (0xFFFFFFFF = no neighbour):
  * S = the ids in the heap after the traversal; every distinct neighbour of
@@ -485,7 +491,8 @@ static float summary_score_exact(const or_index* ix, const double* qd, uint64_t 
 int or_pruned_search(const or_index* ix, const uint64_t* q_ptr, const uint32_t* q_words, uint64_t nq,
                      int k, int cut, float hf, uint32_t flags, int nthreads, int c_cap,
                      uint32_t* out_ids, float* out_scores, uint16_t* out_prefix, uint64_t* out_counters,
-                     const uint16_t* probe, double tau, float* out_hmin, const uint32_t* knn, int kappa) {
+                     const uint16_t* probe, double tau, float* out_hmin, const uint32_t* knn, int kappa,
+                     double qmass) {
     if (k < 1 || cut < 0 || !(hf > 0.0f) || c_cap < 1) return -1;
     double PW[OR_PROBE_WORDS];
     if (probe) probe_unpack(probe, PW);
@@ -520,6 +527,17 @@ int or_pruned_search(const or_index* ix, const uint64_t* q_ptr, const uint32_t* 
             }
             qsort(qe, (size_t)nqe, sizeof(qent), cmp_qent);
             int ncut = (cut == 0 || cut > nqe) ? nqe : cut;
+            if (qmass > 0.0) {
+                /* alpha_q-MSS of the query (Algorithm 2, first step): the
+                   shortest prefix of the value-ordered entries whose mass
+                   reaches qmass * ||q||_1 */
+                double total = 0.0, cum = 0.0;
+                for (int j = 0; j < nqe; ++j) total += qe[j].v;
+                const double target = qmass * total;
+                int m = 0;
+                while (m < nqe && cum < target) cum += qe[m++].v;
+                if (m < ncut) ncut = m;
+            }
             if (ncut > c_cap) { bad = 1; ncut = c_cap; }
             cnt[7] = (uint64_t)ncut;
             int hn = 0;

@@ -165,3 +165,27 @@ def test_near_tie_counter():
     r = ix.pruned_search(qs, k=1, cut=0, heap_factor=1.0)
     c = dict(zip(oracle.COUNTER_NAMES, r["counters"][0]))
     assert c["prune_tests"] == 1 and c["near_tie_tests"] == 1 and list(r["prefix"][0]) == [2]
+
+
+def test_query_mass_cut_is_the_alpha_mss_of_the_query():
+    """alpha_q-MSS cut (Algorithm 2, first step): the cut length equals the
+    size of the query's alpha-MSS computed by the sketching routine, and a
+    hand-worked query stops where the mass first reaches the target."""
+    docs = synth.docs(2000, seed=21)
+    qs = synth.queries(60, seed=21)
+    from paper_2509_24815_amd import Index
+    ix = oracle.Index(Index.build(docs, lam=200, beta=10, gamma=0.4, seed=1).serialize())
+    for alpha in (0.2, 0.5, 0.75, 1.0):
+        r = ix.pruned_search(qs, 10, 0, 0.8, c_cap=400, query_mass=alpha)
+        for i in range(qs.n_rows):
+            t, v = qs.row(i)
+            keep = oracle.alpha_mss(t, v.astype(np.float16), alpha)
+            assert r["counters"][i][7] == keep.sum()
+            assert (r["prefix"][i][keep.sum():] == 0).all()
+    # values 4, 2, 1, 1 (mass 8): alpha 0.5 -> 1 entry, 0.5 + eps -> 2, 0.76 -> 3, 1 -> 4
+    q = synth.make_csr([{0: 1.0, 1: 4.0, 2: 1.0, 3: 2.0}], dim=docs.dim)
+    for alpha, m in ((0.5, 1), (0.5001, 2), (0.76, 3), (1.0, 4)):
+        r = ix.pruned_search(q, 5, 0, 0.8, c_cap=8, query_mass=alpha)
+        assert r["counters"][0][7] == m
+    r = ix.pruned_search(q, 5, 2, 0.8, c_cap=8, query_mass=1.0)  # query_cut still caps
+    assert r["counters"][0][7] == 2
