@@ -80,7 +80,12 @@ typedef struct {
 
 /* Search parameters (inputs of Algorithm 2): k results; query_cut = number
    of largest query coordinates whose lists are visited (0 = all of them),
-   the fixed-size stand-in for the alpha_q-MSS of the query; heap_factor > 0:
+   the fixed-size stand-in for the alpha_q-MSS of the query; query_mass =
+   alpha_q > 0 selects the alpha_q-MSS itself (Definition of alpha-MSS,
+   Section 3.2; Algorithm 2, first step): the largest entries (value desc,
+   term asc) up to the first count whose values sum to at least alpha_q
+   times the query's l1 mass, computed exactly in fp64; query_cut > 0 still
+   caps that count (EINVAL for a negative or NaN query_mass); heap_factor > 0:
    a block whose summary score r satisfies r * heap_factor < heap.min (with a
    full heap) is skipped and ends its list; +INFINITY disables pruning.
 
@@ -100,6 +105,7 @@ typedef struct {
     uint32_t flags; /* 0 or SEISMIC_SEARCH_KNN */
     const uint16_t* probe;
     double probe_tau;
+    double query_mass; /* alpha_q > 0: cut = the query's alpha_q-MSS (see above); 0: query_cut alone */
 } seismic_search_params;
 
 /* flags: refine with the index's kappa-NN graph (Algorithm 2, last block;

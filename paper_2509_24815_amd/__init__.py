@@ -49,7 +49,7 @@ class Index:
 
     def search(self, queries, k: int, query_cut: int, heap_factor: float, *, stats: bool = False,
                prefix_stride: int | None = None, stream=None, ws=None, probe=None, probe_tau: float = 0.0,
-               trace: bool = False, refine: bool = False):
+               trace: bool = False, refine: bool = False, query_mass: float = 0.0):
         """Batched search.  ``queries`` is a binding.Csr (host or device).
         Returns torch tensors on the current device (ids, scores[, prefix,
         counters[, list_hmin, list_term]]).  probe: device tensor of
@@ -74,7 +74,7 @@ class Index:
         binding.seismic_search_batch(self.handle, w, queries, k, query_cut, heap_factor, ids, sc,
                                      prefix, stride, counters, stream, probe=probe, probe_tau=probe_tau,
                                      list_hmin=hmin, list_term=term,
-                                     flags=binding.SEARCH_KNN if refine else 0)
+                                     flags=binding.SEARCH_KNN if refine else 0, query_mass=query_mass)
         if trace:
             return ids, sc, prefix, counters, hmin, term
         if stats:

@@ -42,7 +42,8 @@ class BuildParams(ctypes.Structure):
 
 class SearchParams(ctypes.Structure):
     _fields_ = [("k", ctypes.c_uint32), ("query_cut", ctypes.c_uint32), ("heap_factor", ctypes.c_float),
-                ("flags", ctypes.c_uint32), ("probe", ctypes.c_void_p), ("probe_tau", ctypes.c_double)]
+                ("flags", ctypes.c_uint32), ("probe", ctypes.c_void_p), ("probe_tau", ctypes.c_double),
+                ("query_mass", ctypes.c_double)]
 
 
 class ProbeLoss(ctypes.Structure):
@@ -239,8 +240,8 @@ def seismic_workspace_get_config(ws, n_queries: int) -> dict:
     return {"threads": c.threads, "blocks_per_cu": c.blocks_per_cu, "window": c.window}
 
 
-def _params(k, query_cut, heap_factor, flags=0, probe=None, probe_tau=0.0):
-    p = SearchParams(k, query_cut, heap_factor, flags, _ptr(probe), float(probe_tau))
+def _params(k, query_cut, heap_factor, flags=0, probe=None, probe_tau=0.0, query_mass=0.0):
+    p = SearchParams(k, query_cut, heap_factor, flags, _ptr(probe), float(probe_tau), float(query_mass))
     p._keep = probe
     return p
 
@@ -261,10 +262,10 @@ def seismic_autotune(handle, ws, queries: Csr, k: int, query_cut: int, heap_fact
 def seismic_search_batch(handle, ws, queries: Csr, k: int, query_cut: int, heap_factor: float,
                          out_ids, out_scores, prefix=None, prefix_stride: int = 0, counters=None,
                          stream=None, flags: int = 0, probe=None, probe_tau: float = 0.0,
-                         list_hmin=None, list_term=None):
+                         list_hmin=None, list_term=None, query_mass: float = 0.0):
     """probe: device tensor of PROBE_WORDS bf16 words (int16/uint16/bfloat16)
     or None; list_hmin (float32) / list_term (int32) [n * prefix_stride]."""
-    p = _params(k, query_cut, heap_factor, flags, probe, probe_tau)
+    p = _params(k, query_cut, heap_factor, flags, probe, probe_tau, query_mass)
     st = Stats(_ptr(prefix), prefix_stride, 0, _ptr(counters), _ptr(list_hmin), _ptr(list_term))
     use_stats = any(x is not None for x in (prefix, counters, list_hmin, list_term))
     _check(load().seismic_search_batch(handle, ws, ctypes.byref(queries), ctypes.byref(p), _ptr(out_ids),

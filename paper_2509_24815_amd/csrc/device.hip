@@ -115,6 +115,7 @@ int check_params(const seismic_index* index, const seismic_workspace* ws, const 
                         params->k, index->dev->kappa);
     }
     if (params->probe && !(params->probe_tau == params->probe_tau)) return fail(SEISMIC_EINVAL, "search: probe_tau is NaN");
+    if (!(params->query_mass >= 0.0)) return fail(SEISMIC_EINVAL, "search: query_mass must be >= 0");
     if (queries->dim != index->h.dim) return fail(SEISMIC_EINVAL, "search: query dim %u != index dim %u", queries->dim, index->h.dim);
     if (queries->n_rows > ws->max_queries)
         return fail(SEISMIC_EINVAL, "search: %llu queries exceed the workspace (%u)", (unsigned long long)queries->n_rows, ws->max_queries);
@@ -134,6 +135,7 @@ int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64
     a.q_nnz = nnz;
     a.k = params->k;
     a.cut = params->query_cut;
+    a.qmass = params->query_mass;
     a.hf = params->heap_factor;
     a.sort_cap = index->dev->sort_cap;
     a.nq = (uint32_t)nq;

@@ -577,7 +577,7 @@ __global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
         const uint64_t q1 = min(a.q_ptr[qi + 1], a.q_nnz), q0 = min(a.q_ptr[qi], q1);
         const uint64_t raw = q1 - q0;
         const uint32_t nqe = (uint32_t)min<uint64_t>(raw, (uint64_t)kMaxQ);
-        if (tid < 8) L.misc[tid] = 0;
+        if (tid < 12) L.misc[tid] = 0;  // 8..9: query mass (fp64), 10: alpha_q-MSS size
         __syncthreads();
         uint32_t st = (raw > (uint64_t)kMaxQ) ? 4u : 0u;
         for (uint32_t j = tid; j < nqe; j += NT) {
@@ -599,12 +599,19 @@ __global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
         __syncthreads();
         build_prefix<NT>(L.bq.bits, L.bq.pref, nw, L.scratch);
         uint32_t nvalid_local = 0;
-        for (uint32_t j = tid; j < nqe; j += NT) nvalid_local += L.q_term[j] != 0xFFFFu ? 1u : 0u;
+        double mass_local = 0.0;
+        for (uint32_t j = tid; j < nqe; j += NT) {
+            const bool v = L.q_term[j] != 0xFFFFu;
+            nvalid_local += v ? 1u : 0u;
+            if (v) mass_local += (double)half_bits_to_float(L.q_half[j]);
+        }
         if (nvalid_local) atomicAdd(&L.misc[1], nvalid_local);
+        if (a.qmass > 0.0 && mass_local != 0.0) atomicAdd((double*)&L.misc[8], mass_local);
         __syncthreads();
         const uint32_t nvalid = L.misc[1];
         const bool u8mode = nvalid <= kMaxSlots;
-        const uint32_t ncut = (a.cut == 0 || a.cut > nvalid) ? nvalid : a.cut;
+        const uint32_t ncut0 = (a.cut == 0 || a.cut > nvalid) ? nvalid : a.cut;
+        const double mass_target = a.qmass * *(const double*)&L.misc[8];
         // slot of every valid entry (1-based rank of its term)
         uint32_t my_slot[kMaxQ / NT];
 #pragma unroll
@@ -619,21 +626,31 @@ __global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
             my_slot[r] = slot + 1;
             if (u8mode) L.qv[slot + 1] = (double)half_bits_to_float(L.q_half[j]);
         }
-        // cut order: value desc (positive fp16: bit order), then term asc
+        // cut order: value desc (positive fp16: bit order), then term asc.
+        // With alpha_q > 0 the cut also stops at the alpha_q-MSS of the query:
+        // an entry belongs to it while the mass ranked before it is below
+        // alpha_q * ||q||_1 (exact fp64 sums).
+        uint32_t in_mss = 0;
         for (uint32_t j = tid; j < nqe; j += NT) {
             const uint32_t t = L.q_term[j];
             if (t == 0xFFFFu) continue;
             const uint32_t h = L.q_half[j];
             uint32_t rank = 0;
+            double before = 0.0;
             for (uint32_t i = 0; i < nqe; ++i) {
                 const uint32_t ti = L.q_term[i];
                 const uint32_t hi = L.q_half[i];
-                rank += (ti != 0xFFFFu && (hi > h || (hi == h && ti < t))) ? 1u : 0u;
+                const bool b = ti != 0xFFFFu && (hi > h || (hi == h && ti < t));
+                rank += b ? 1u : 0u;
+                if (b && a.qmass > 0.0) before += (double)half_bits_to_float(hi);
             }
-            if (rank < ncut) L.cut[rank] = (uint16_t)t;
+            if (rank < ncut0) L.cut[rank] = (uint16_t)t;
+            if (a.qmass > 0.0 && before < mass_target) ++in_mss;
         }
+        if (in_mss) atomicAdd(&L.misc[10], in_mss);
         const uint32_t status = L.misc[0];
         __syncthreads();
+        const uint32_t ncut = a.qmass > 0.0 ? min(ncut0, L.misc[10]) : ncut0;
         if (u8mode) {
             // bitmap + prefix -> slot table
             for (uint32_t i = tid; i < (10 * nw + 15) / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);

@@ -22,6 +22,7 @@ struct SearchArgs {
     const uint32_t* nq_dev;  // optional device word holding the batch size (<= nq), read at launch
     uint32_t k;
     uint32_t cut;
+    double qmass;       // alpha_q of the query's alpha_q-MSS cut (0: query_cut alone)
     float hf;
     uint32_t sort_cap;  // power of two >= the largest list's block count
     uint32_t window;    // speculation window W in blocks, 1..kMaxW

@@ -182,3 +182,25 @@ def test_autotune_keeps_results_and_picks_a_shape(cfg1):
     with pytest.raises(SeismicError):
         binding.seismic_workspace_set_config(ws, window=0)
     binding.seismic_workspace_free(ws)
+
+
+@pytest.mark.parametrize("alpha,cut", [(0.3, 0), (0.6, 0), (1.0, 0), (0.5, 10)])
+def test_query_mass_cut_parity(cfg1, alpha, cut):
+    """alpha_q-MSS query cut: ids, scores, prefix lengths and counters
+    (including the cut length) equal the oracle's."""
+    docs, qs, ix, ref_ix = cfg1
+    _log(f"[query mass] alpha_q={alpha} cut={cut}")
+    stride = 400
+    ref = ref_ix.pruned_search(qs, 10, cut, 0.8, c_cap=stride, query_mass=alpha)
+    gpu = ix.search(to_device_csr(qs), 10, cut, 0.8, stats=True, prefix_stride=stride, query_mass=alpha)
+    assert not compare_with_oracle(gpu, ref, 10, stride)
+    _log(f"  mean cut length {ref['counters'][:, 7].mean():.2f}")
+
+
+def test_query_mass_argument_errors(cfg1):
+    docs, qs, ix, _ = cfg1
+    sub = to_device_csr(qs.subset(range(4)))
+    for bad in (-0.5, float("nan")):
+        with pytest.raises(SeismicError) as e:
+            ix.search(sub, 10, 10, 0.8, query_mass=bad)
+        assert e.value.code == binding.EINVAL
