@@ -76,6 +76,8 @@ typedef struct {
     uint64_t seed;
     int32_t n_threads;
     int32_t verbose;
+    double alpha; /* 0: fixed caps; in (0, 1]: a column of n nonzeros keeps at most
+                     min(lambda, ceil(alpha * n)) (the paper's proportional Set alpha-MSS) */
 } seismic_build_params;
 
 /* Search parameters (inputs of Algorithm 2): k results; query_cut = number

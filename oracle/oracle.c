@@ -69,6 +69,7 @@ typedef struct {
     uint64_t n_docs, nnz, n_blocks, n_postings, n_summary;
     uint32_t lambda, beta;
     double gamma;
+    double alpha; /* > 0: proportional caps ceil(alpha * |L_i|) (header offset 88) */
     uint64_t seed;
     uint32_t qbits;
     const uint64_t* row_ptr;
@@ -102,6 +103,7 @@ static int parse(or_index* ix, const uint8_t* base, uint64_t size) {
     memcpy(&ix->n_summary, base + 48, 8);
     memcpy(&ix->lambda, base + 56, 4);
     memcpy(&ix->beta, base + 60, 4);
+    memcpy(&ix->alpha, base + 88, 8);
     memcpy(&ix->gamma, base + 64, 8);
     memcpy(&ix->seed, base + 72, 8);
     memcpy(&ix->qbits, base + 80, 4);
@@ -748,9 +750,10 @@ static double doc_dot_doc(const or_index* ix, uint32_t a, uint32_t b) {
 
 /*
  * Check a serialized index against the indexing algorithm of Section 4.4
- * with a fixed list cap lambda.  Returns 0 when every check passes, 1 with
- * a message otherwise.
- *   - list i holds the min(|L_i|, lambda) largest values of column i
+ * with a fixed list cap lambda, or the proportional cap ceil(alpha * |L_i|)
+ * (at most lambda) when the header's alpha is > 0.  Returns 0 when every
+ * check passes, 1 with a message otherwise.
+ *   - list i holds the min(|L_i|, cap_i) largest values of column i
  *     (value desc, doc id asc);
  *   - its blocks partition that list: at least 1 and at most
  *     max(1, ceil(beta * n_i / lambda)) of them, none empty, doc ids
@@ -797,8 +800,16 @@ int or_check_index(const or_index* ix, int check_clustering, int term_stride, ch
         uint32_t b0 = ix->list_off[t], b1 = ix->list_off[t + 1];
         uint32_t nb = b1 - b0;
         if (keep_cap < n_full) { keep_cap = n_full; keep = (uint8_t*)realloc(keep, keep_cap); }
-        or_column_keep(col_id + cnt[t], col_h + cnt[t], n_full, ix->lambda, keep);
-        uint64_t n = n_full < ix->lambda ? n_full : ix->lambda;
+        /* the column's cap: lambda, and with alpha > 0 ceil(alpha * |L_i|)
+           (Set alpha-MSS, Section 3.4), at least 1 */
+        uint64_t cap = ix->lambda;
+        if (ix->alpha > 0.0) {
+            double c = ceil(ix->alpha * (double)n_full);
+            uint64_t pc = c < 1.0 ? 1 : (uint64_t)c;
+            if (pc < cap) cap = pc;
+        }
+        or_column_keep(col_id + cnt[t], col_h + cnt[t], n_full, cap, keep);
+        uint64_t n = n_full < cap ? n_full : cap;
         if (n == 0) {
             if (nb != 0) FAIL("term %u: empty list has %u blocks", t, nb);
             continue;

@@ -21,9 +21,9 @@ class Index:
 
     @classmethod
     def build(cls, docs, lam: int, beta: int, gamma: float, seed: int = 0, n_threads: int = 0,
-              verbose: bool = False) -> "Index":
+              verbose: bool = False, alpha: float = 0.0) -> "Index":
         return cls(binding.seismic_build_index(docs.row_ptr, docs.words, docs.dim, lam, beta, gamma, seed,
-                                               n_threads, int(verbose)))
+                                               n_threads, int(verbose), alpha))
 
     @classmethod
     def load(cls, path: str) -> "Index":

@@ -37,7 +37,8 @@ class Csr(ctypes.Structure):
 
 class BuildParams(ctypes.Structure):
     _fields_ = [("lam", ctypes.c_uint32), ("beta", ctypes.c_uint32), ("gamma", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("n_threads", ctypes.c_int32), ("verbose", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("n_threads", ctypes.c_int32), ("verbose", ctypes.c_int32),
+                ("alpha", ctypes.c_double)]
 
 
 class SearchParams(ctypes.Structure):
@@ -173,10 +174,10 @@ def _stream_handle(stream) -> int:
 
 # ----------------------------------------------------------------- C names
 
-def seismic_build_index(row_ptr, words, dim, lam, beta, gamma, seed=0, n_threads=0, verbose=0) -> int:
+def seismic_build_index(row_ptr, words, dim, lam, beta, gamma, seed=0, n_threads=0, verbose=0, alpha=0.0) -> int:
     lib = load()
     csr = host_csr(row_ptr, words, dim)
-    p = BuildParams(lam, beta, gamma, seed, n_threads, verbose)
+    p = BuildParams(lam, beta, gamma, seed, n_threads, verbose, alpha)
     h = ctypes.c_void_p()
     _check(lib.seismic_build_index(ctypes.byref(csr), ctypes.byref(p), ctypes.byref(h)))
     return h.value

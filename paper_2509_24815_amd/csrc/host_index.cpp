@@ -216,24 +216,42 @@ void quantize_block(const uint16_t* vals, size_t n, float& m_out, float& d_out, 
     d_out = (float)std::ldexp((double)d_u, -24);
 }
 
+}  // namespace
+
+// Entries kept of a column of n_full nonzeros (Set alpha-MSS, Section 3.4):
+// the fixed cap lambda, and with alpha > 0 also at most ceil(alpha * n_full)
+// (the proportional form), at least 1.
+uint64_t list_cap(uint64_t n_full, uint32_t lambda, double alpha) {
+    uint64_t cap = lambda;
+    if (alpha > 0.0) {
+        const double c = std::ceil(alpha * (double)n_full);
+        const uint64_t pc = c < 1.0 ? 1 : (uint64_t)c;
+        if (pc < cap) cap = pc;
+    }
+    return cap;
+}
+
+namespace {
+
 void build_term(uint32_t t, const HostCSC& csc, const uint64_t* row_ptr, const uint32_t* words,
                 const seismic_build_params& p, uint32_t dim, Scratch& S, TermOut& out) {
     const uint64_t a = csc.off[t], b = csc.off[t + 1];
     const uint64_t n_full = b - a;
     if (n_full == 0) return;
-    // Set alpha-MSS, fixed cap: keep the lambda largest values of the column
-    // (value desc, doc id asc); the kept list is stored doc-ascending.
+    // Set alpha-MSS: keep the cap largest values of the column (value desc,
+    // doc id asc); the kept list is stored doc-ascending.
+    const uint64_t cap = list_cap(n_full, p.lambda, p.alpha);
     std::vector<uint32_t> list;
-    if (n_full <= p.lambda) {
+    if (n_full <= cap) {
         list.assign(csc.doc.begin() + a, csc.doc.begin() + b);
     } else {
         S.col.resize(n_full);
         for (uint64_t i = 0; i < n_full; ++i)  // key: larger value first, then smaller id
             S.col[i] = {~half_units24(csc.val[a + i]), csc.doc[a + i]};
-        std::nth_element(S.col.begin(), S.col.begin() + (p.lambda - 1), S.col.end());
-        // nth_element leaves the smallest lambda keys (by pair order) in front
-        list.resize(p.lambda);
-        for (uint32_t i = 0; i < p.lambda; ++i) list[i] = S.col[i].second;
+        std::nth_element(S.col.begin(), S.col.begin() + (cap - 1), S.col.end());
+        // nth_element leaves the smallest cap keys (by pair order) in front
+        list.resize(cap);
+        for (uint64_t i = 0; i < cap; ++i) list[i] = S.col[i].second;
         std::sort(list.begin(), list.end());
     }
     const uint64_t n = list.size();
@@ -360,6 +378,7 @@ int build_host_index(const seismic_csr* docs, const seismic_build_params* p, Hos
     if (p->lambda < 1) return fail(SEISMIC_EINVAL, "build: lambda must be >= 1");
     if (p->beta < 1) return fail(SEISMIC_EINVAL, "build: beta must be >= 1");
     if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return fail(SEISMIC_EINVAL, "build: gamma must be in (0, 1]");
+    if (!(p->alpha >= 0.0 && p->alpha <= 1.0)) return fail(SEISMIC_EINVAL, "build: alpha must be in [0, 1]");
     int rc = validate_csr_host(docs, 65536, "build: docs");
     if (rc) return rc;
     if (docs->n_rows >= 0xFFFFFFFFull) return fail(SEISMIC_EINVAL, "build: more than 2^32-1 documents");
@@ -373,6 +392,7 @@ int build_host_index(const seismic_csr* docs, const seismic_build_params* p, Hos
         H.beta = p->beta;
         H.gamma = p->gamma;
         H.seed = p->seed;
+        H.alpha = p->alpha;
         H.row_ptr.assign(docs->row_ptr, docs->row_ptr + docs->n_rows + 1);
         H.words.assign(docs->words, docs->words + docs->nnz);
         auto t_start = std::chrono::steady_clock::now();
@@ -387,21 +407,21 @@ int build_host_index(const seismic_csr* docs, const seismic_build_params* p, Hos
         std::vector<uint32_t> terms(dim);
         std::iota(terms.begin(), terms.end(), 0u);
         std::sort(terms.begin(), terms.end(), [&](uint32_t x, uint32_t y) {
-            uint64_t nx = std::min<uint64_t>(csc.off[x + 1] - csc.off[x], p->lambda);
-            uint64_t ny = std::min<uint64_t>(csc.off[y + 1] - csc.off[y], p->lambda);
+            uint64_t nx = std::min<uint64_t>(csc.off[x + 1] - csc.off[x], list_cap(csc.off[x + 1] - csc.off[x], p->lambda, p->alpha));
+            uint64_t ny = std::min<uint64_t>(csc.off[y + 1] - csc.off[y], list_cap(csc.off[y + 1] - csc.off[y], p->lambda, p->alpha));
             return nx != ny ? nx > ny : x < y;
         });
         std::vector<std::unique_ptr<Scratch>> scratch(nthreads);
         for (auto& s : scratch) s.reset(new Scratch(dim));
         uint64_t total_work = 0;
-        for (uint32_t t = 0; t < dim; ++t) total_work += std::min<uint64_t>(csc.off[t + 1] - csc.off[t], p->lambda);
+        for (uint32_t t = 0; t < dim; ++t) total_work += std::min<uint64_t>(csc.off[t + 1] - csc.off[t], list_cap(csc.off[t + 1] - csc.off[t], p->lambda, p->alpha));
         std::atomic<uint64_t> done_work{0};
         std::atomic<int> reported{0};
         parallel_for(dim, nthreads, 1, [&](int64_t i, int tid) {
             uint32_t t = terms[i];
             build_term(t, csc, H.row_ptr.data(), H.words.data(), *p, dim, *scratch[tid], outs[t]);
             if (p->verbose && total_work) {
-                uint64_t w = std::min<uint64_t>(csc.off[t + 1] - csc.off[t], p->lambda);
+                uint64_t w = std::min<uint64_t>(csc.off[t + 1] - csc.off[t], list_cap(csc.off[t + 1] - csc.off[t], p->lambda, p->alpha));
                 uint64_t d = done_work.fetch_add(w) + w;
                 int pct = (int)(100 * d / total_work);
                 int prev = reported.load();
@@ -501,6 +521,7 @@ void serialize(const HostIndex& h, uint8_t* buf) {
     std::memcpy(head + 64, &h.gamma, 8);
     std::memcpy(head + 72, &h.seed, 8);
     u32 = kGridBits; std::memcpy(head + 80, &u32, 4);
+    std::memcpy(head + 88, &h.alpha, 8);
     std::memcpy(buf, head, kHeaderBytes);
     SectionView s[11];
     sections_of(h, s);
@@ -533,6 +554,8 @@ int deserialize(const uint8_t* buf, uint64_t size, HostIndex& h) {
     std::memcpy(&h.gamma, buf + 64, 8);
     std::memcpy(&h.seed, buf + 72, 8);
     std::memcpy(&grid, buf + 80, 4);
+    std::memcpy(&h.alpha, buf + 88, 8);
+    if (!(h.alpha >= 0.0 && h.alpha <= 1.0)) return fail(SEISMIC_EFORMAT, "index: alpha out of range");
     if (grid != kGridBits) return fail(SEISMIC_EFORMAT, "index: unsupported quantization grid");
     if (h.dim < 1 || h.dim > 65536 || h.n_docs >= 0xFFFFFFFFull || np >= 0xFFFFFFFFull || nb >= 0xFFFFFFFFull)
         return fail(SEISMIC_EFORMAT, "index: header out of range");

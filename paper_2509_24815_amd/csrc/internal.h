@@ -76,7 +76,8 @@ int resolve_threads(int requested);
 
 // Serialized format, version 1 (little-endian).  A 128-byte header
 //   "SEISMIC\0", u32 version, u32 dim, u64 n_docs, nnz, n_blocks, n_postings,
-//   n_summary, u32 lambda, u32 beta, f64 gamma, u64 seed, u32 grid bits (14)
+//   n_summary, u32 lambda, u32 beta, f64 gamma, u64 seed, u32 grid bits (14),
+//   u32 zero, f64 alpha (0 = fixed caps; older files hold 0 there)
 // followed by 11 sections, each at a 64-byte aligned offset:
 //   row_ptr u64[n_docs+1], words u32[nnz], list_off u32[dim+1],
 //   blk_post_off u32[nb+1], blk_sum_off u64[nb+1], blk_m f32[nb],
@@ -92,6 +93,7 @@ struct HostIndex {
     uint32_t lambda = 0, beta = 0;
     double gamma = 0.0;
     uint64_t seed = 0;
+    double alpha = 0.0;  // > 0: proportional list caps (Set alpha-MSS)
     std::vector<uint64_t> row_ptr;      // forward index (Section 4.2)
     std::vector<uint32_t> words;
     std::vector<uint32_t> list_off;     // dim+1: blocks of term t are [list_off[t], list_off[t+1])
@@ -120,6 +122,7 @@ int validate_csr_host(const seismic_csr* m, uint32_t max_row_nnz, const char* wh
 void build_csc(const uint64_t* row_ptr, const uint32_t* words, uint64_t n_docs, uint32_t dim, int nthreads,
                HostCSC& out);
 int build_host_index(const seismic_csr* docs, const seismic_build_params* p, HostIndex& out);
+uint64_t list_cap(uint64_t n_full, uint32_t lambda, double alpha);
 uint64_t serialized_size(const HostIndex& h);
 void serialize(const HostIndex& h, uint8_t* buf);
 int deserialize(const uint8_t* buf, uint64_t size, HostIndex& out);

@@ -1,6 +1,7 @@
 """Host-side tests of libseismic: exported symbols, the index builder checked
 by the oracle, the serialized format and error paths.  No GPU needed."""
 import ctypes
+import math
 import os
 import re
 
@@ -117,3 +118,43 @@ def test_empty_and_degenerate_collections():
     info = ix.info()
     assert info["n_blocks"] == 1 and info["n_postings"] == 1
     assert oracle.Index(ix.serialize()).check() == ""
+
+
+def test_proportional_caps_reproduce_fig3_and_pass_the_check():
+    """Set alpha-MSS in its proportional form (Section 3.4): with alpha 0.4
+    each column keeps its ceil(0.4 |L_i|) largest values.  The library's
+    build of the Figure "set-sketch" matrix keeps the figure's values
+    (column 7 of the figure is defective, ties may break either way), and
+    the oracle's structure check accepts it."""
+    from tests.test_oracle_sketch import _read_fig3
+    before, after = _read_fig3()
+    rows = [{int(c): float(v) for c, v in enumerate(r) if v} for r in before]
+    docs = synth.make_csr(rows, dim=8)
+    ix = Index.build(docs, lam=1000, beta=1, gamma=1.0, seed=0, alpha=0.4)
+    ref = oracle.Index(ix.serialize())
+    assert ref.check() == ""
+    S = ref.sections()
+    for c in range(8):
+        b0, b1 = int(S["list_off"][c]), int(S["list_off"][c + 1])
+        kept = sorted(int(d) for d in S["postings"][S["blk_post_off"][b0]:S["blk_post_off"][b1]])
+        nz = np.nonzero(before[:, c])[0]
+        assert len(kept) == math.ceil(0.4 * len(nz) - 1e-12)
+        if c == 6:
+            continue
+        assert sorted(before[kept, c]) == sorted(after[:, c][np.nonzero(after[:, c])[0]]), f"column {c + 1}"
+
+
+def test_proportional_caps_random_collection():
+    docs = synth.docs(3000, seed=31)
+    ix = Index.build(docs, lam=400, beta=20, gamma=0.4, seed=3, alpha=0.3)
+    ref = oracle.Index(ix.serialize())
+    assert ref.check(clustering=True) == ""
+    # caps: min(lambda, ceil(0.3 n)) per column
+    S = ref.sections()
+    counts = np.bincount((docs.words & 0xFFFF).astype(np.int64), minlength=docs.dim)
+    for t in np.nonzero(counts)[0][::37]:
+        b0, b1 = int(S["list_off"][t]), int(S["list_off"][t + 1])
+        n = int(S["blk_post_off"][b1] - S["blk_post_off"][b0])
+        assert n == min(400, max(1, math.ceil(0.3 * int(counts[t]))))
+    with pytest.raises(SeismicError):
+        Index.build(docs, lam=400, beta=20, gamma=0.4, alpha=1.5)
