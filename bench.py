@@ -134,6 +134,10 @@ def main():
     ap.add_argument("--index-cache", default=None, help="load the index from this file if present, else build and save")
     ap.add_argument("--plain-rows", action="store_true", help="search the forward rows in place (no block-major copies)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--alpha", type=float, default=0.0,
+                    help="proportional list caps ceil(alpha |L_i|) at build time (0 = fixed lambda)")
+    ap.add_argument("--query-mass", type=float, default=0.0,
+                    help="search with the alpha_q-MSS query cut of this mass fraction instead of query_cut")
     ap.add_argument("--grid", default="", help="also sweep query_cut x heap_factor, e.g. '5,10,20x0.7,0.8,0.9'")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--knn", type=int, default=20, help="kappa of the kappa-NN graph for the refined form (0 = skip)")
@@ -176,7 +180,8 @@ def main():
         build_s = None
         log(f"[bench] index loaded from {cache} in {time.time() - t1:.1f} s")
     else:
-        ix = Index.build(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, verbose=True)
+        ix = Index.build(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, verbose=True,
+                         alpha=args.alpha)
         build_s = time.time() - t1
         log(f"[bench] index built in {build_s:.1f} s")
         if cache:
@@ -193,7 +198,7 @@ def main():
         log(f"[bench] block-major rows unavailable ({e}); plain rows")
         ix.close()
         ix = Index.load(cache) if cache and os.path.exists(cache) else \
-            Index.build(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads)
+            Index.build(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, alpha=args.alpha)
         ix.upload(0)
         layout = "rows"
     log(f"[bench] index resident in HBM ({layout}, {time.time() - t1:.1f} s)")
@@ -207,9 +212,10 @@ def main():
     binding.seismic_workspace_set_config(ws, 256, 0, 8)
     out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     out_sc = torch.empty((nq, k), dtype=torch.float32, device=dev)
-    cut = W["cut"]
+    cut = 0 if args.query_mass > 0 else W["cut"]
+    qmass = args.query_mass
     grid_cuts = sorted({int(c) for c in args.grid.split("x")[0].split(",")}) if args.grid else []
-    prefix = torch.zeros((nq, max([cut] + grid_cuts)), dtype=torch.int16, device=dev)
+    prefix = torch.zeros((nq, max([cut or binding.MAX_QUERY_NNZ] + grid_cuts)), dtype=torch.int16, device=dev)
     counters = torch.zeros((nq, 8), dtype=torch.int64, device=dev)
 
     # ground truth
@@ -236,11 +242,11 @@ def main():
         return float(np.mean(strict)), float(np.mean(tie))
 
     def run(hf, with_stats, probe=None, tau=0.0, c=None, flags=0):
-        c = c or cut
+        c = cut if c is None else c
         binding.seismic_search_batch(ix.handle, ws, qcsr, k, c, hf, out_ids, out_sc,
-                                     prefix if with_stats else None, c if with_stats else 0,
+                                     prefix if with_stats else None, prefix.shape[1] if with_stats else 0,
                                      counters if with_stats else None, stream, probe=probe, probe_tau=tau,
-                                     flags=flags)
+                                     flags=flags, query_mass=qmass)
 
     def measure(hf, probe=None, tau=0.0, c=None, flags=0):
         run(hf, True, probe, tau, c, flags)
@@ -487,7 +493,7 @@ def main():
         log(f"[bench] CPU baseline {cpu}")
         del ref, buf
 
-    traffic = measured_traffic(args.workload, chosen, k)
+    traffic = measured_traffic(args.workload, chosen, k) if not (args.alpha or qmass) else None
     out = {
         "metric": "QPS at Recall@10>=0.95 (1 GPU, 8.8M docs); p50/p99 query latency",
         "value": round(qps, 1),
@@ -502,8 +508,10 @@ def main():
         "dtype": "f16xf16->f64 accumulate, f32 out",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {W['n_docs']} docs, {nq}-query batch ({W['qlaw']} nnz), "
-                               f"lambda {W['lam']}, beta {W['beta']}, gamma {W['gamma']}, query_cut {cut}, "
-                               f"k {k}, heap_factor {chosen}",
+                               f"lambda {W['lam']}, beta {W['beta']}, gamma {W['gamma']}, "
+                               + (f"alpha {args.alpha}, " if args.alpha else "")
+                               + (f"query_mass {qmass}, " if qmass else f"query_cut {cut}, ")
+                               + f"k {k}, heap_factor {chosen}",
                    f"recall_at_{k}": point["recall"], "recall_target": args.recall,
                    "index_build_s": None if build_s is None else round(build_s, 1),
                    "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,

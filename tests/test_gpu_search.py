@@ -204,3 +204,19 @@ def test_query_mass_argument_errors(cfg1):
         with pytest.raises(SeismicError) as e:
             ix.search(sub, 10, 10, 0.8, query_mass=bad)
         assert e.value.code == binding.EINVAL
+
+
+def test_mass_based_variants_parity():
+    """Both mass-based knobs of the paper: proportional list caps at build
+    time (alpha) and the alpha_q-MSS query cut at search time."""
+    _log("[mass variants] 30k docs, alpha 0.3, query_mass 0.5")
+    docs = synth.docs(30_000, seed=12)
+    qs = synth.queries(300, seed=12)
+    ix = Index.build(docs, lam=3000, beta=60, gamma=0.4, seed=12, alpha=0.3)
+    ref = oracle.Index(ix.serialize())
+    assert ref.check(clustering=False, term_stride=7) == ""
+    ix.upload(0, block_rows=True)
+    for qm, cut in ((0.5, 0), (0.8, 12)):
+        r = ref.pruned_search(qs, 10, cut, 0.8, c_cap=400, query_mass=qm)
+        gpu = ix.search(to_device_csr(qs), 10, cut, 0.8, stats=True, prefix_stride=400, query_mass=qm)
+        assert not compare_with_oracle(gpu, r, 10, 400)
