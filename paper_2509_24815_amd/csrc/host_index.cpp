@@ -343,10 +343,28 @@ void build_term(uint32_t t, const HostCSC& csc, const uint64_t* row_ptr, const u
             S.ent.push_back({~u, tt});
             total += std::ldexp((double)u, -24);
         }
-        std::sort(S.ent.begin(), S.ent.end());
+        // The kept prefix is found by selection, not a full sort: halve the
+        // candidate range [lo, hi) around its rank-median (nth_element) while
+        // tracking the mass of the best elements known to be kept; the sums
+        // are exact, so the boundary equals the one of the sorted scan.
         const double need = p.gamma * total;
-        double cum = 0.0;
-        size_t keep = 0;
+        size_t lo = 0, hi = S.ent.size();
+        double before = 0.0;  // mass of ent[0, lo): all kept
+        while (hi - lo > 32) {
+            const size_t mid = lo + (hi - lo) / 2;
+            std::nth_element(S.ent.begin() + lo, S.ent.begin() + mid, S.ent.begin() + hi);
+            double m = 0.0;
+            for (size_t i = lo; i <= mid; ++i) m += std::ldexp((double)(~S.ent[i].first), -24);
+            if (before + m >= need) {
+                hi = mid + 1;
+            } else {
+                before += m;
+                lo = mid + 1;
+            }
+        }
+        std::sort(S.ent.begin() + lo, S.ent.begin() + hi);
+        double cum = before;
+        size_t keep = lo;
         while (keep < S.ent.size()) {
             cum += std::ldexp((double)(~S.ent[keep].first), -24);
             ++keep;
