@@ -158,6 +158,18 @@ const char* seismic_last_error(void);
    parameters, ENOMEM on allocation failure. */
 int seismic_build_index(const seismic_csr* docs, const seismic_build_params* params, seismic_index** out);
 
+/* The same build with the per-list work (Set alpha-MSS selection, centroid
+   sampling, K-means assignment, blocks, gamma-MSS summaries, quantization)
+   on HIP device `device`; the inverted lists are formed on the host.  For
+   values in [2^-6, 2^6] every inner product of the assignment is exact, so
+   the index is byte for byte the host build's.  Lists beyond the GPU path's
+   capacities (more than 1024 blocks in a list, more than 2048 entries tied
+   at a summary's mass boundary, more than 4096 entries in one summary) make
+   it fall back to seismic_build_index.  Synchronous; the index is returned
+   in host memory like seismic_build_index's (upload it to search). */
+int seismic_build_index_gpu(const seismic_csr* docs, const seismic_build_params* params, int device,
+                            seismic_index** out);
+
 /* Serialized form (format version 1, little-endian): see DESIGN notes in
    the source.  save writes a file; serialize writes into a caller buffer of
    seismic_index_serialized_size() bytes.  EIO on write failure. */

@@ -26,6 +26,13 @@ class Index:
                                                n_threads, int(verbose), alpha))
 
     @classmethod
+    def build_gpu(cls, docs, lam: int, beta: int, gamma: float, seed: int = 0, n_threads: int = 0,
+                  verbose: bool = False, alpha: float = 0.0, device: int = 0) -> "Index":
+        """The same index, with the per-list work on the GPU."""
+        return cls(binding.seismic_build_index_gpu(docs.row_ptr, docs.words, docs.dim, lam, beta, gamma, seed,
+                                                   n_threads, int(verbose), alpha, device))
+
+    @classmethod
     def load(cls, path: str) -> "Index":
         return cls(binding.seismic_index_load(path))
 
