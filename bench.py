@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--index-cache", default=None, help="load the index from this file if present, else build and save")
     ap.add_argument("--plain-rows", action="store_true", help="search the forward rows in place (no block-major copies)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--host-build", action="store_true",
+                    help="build the index on the host (default: the GPU build, byte-identical)")
     ap.add_argument("--alpha", type=float, default=0.0,
                     help="proportional list caps ceil(alpha |L_i|) at build time (0 = fixed lambda)")
     ap.add_argument("--query-mass", type=float, default=0.0,
@@ -180,8 +182,9 @@ def main():
         build_s = None
         log(f"[bench] index loaded from {cache} in {time.time() - t1:.1f} s")
     else:
-        ix = Index.build(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, verbose=True,
-                         alpha=args.alpha)
+        builder = Index.build if args.host_build else Index.build_gpu
+        ix = builder(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, verbose=True,
+                     alpha=args.alpha)
         build_s = time.time() - t1
         log(f"[bench] index built in {build_s:.1f} s")
         if cache:
@@ -514,6 +517,7 @@ def main():
                                + f"k {k}, heap_factor {chosen}",
                    f"recall_at_{k}": point["recall"], "recall_target": args.recall,
                    "index_build_s": None if build_s is None else round(build_s, 1),
+                   "index_build": "cached" if build_s is None else ("host" if args.host_build else "gpu"),
                    "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
                    "sweep": sweep, "learned_probe": learned, "knn_refined": refined, "grid": grid},
         "serving": serving,
