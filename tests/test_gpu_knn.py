@@ -8,7 +8,9 @@ import pytest
 
 import oracle
 import synth
+from oracle import mlp
 from paper_2509_24815_amd import Index, SeismicError, binding
+from paper_2509_24815_amd import probe as P
 from tests.gpu_util import as_u32, compare_with_oracle, to_device_csr
 
 pytestmark = pytest.mark.gpu
@@ -71,6 +73,30 @@ def test_refinement_with_search_built_graph_raises_recall(idx):
     p_ids, _ = ix.search(to_device_csr(qs), 10, 5, 0.4)
     _log(f"  Recall@10 cut 5 hf 0.4: plain {rec(as_u32(p_ids)):.4f}, refined {rec(as_u32(ids)):.4f}")
     assert rec(as_u32(ids)) > rec(as_u32(p_ids))
+
+
+@pytest.mark.parametrize("tau,qmass,cut", [(-1.0, 0.0, 10), (0.0, 0.5, 30), (1.0, 0.3, 30)])
+def test_refined_learned_search_parity(idx, tau, qmass, cut):
+    """Every mode at once: the learned probe decides block visits, the
+    alpha_q-MSS cut (or the fixed cut) selects lists, and the graph refines
+    the result; ids, scores, counters and per-list heap minima as the
+    oracle's."""
+    docs, qs, ix, ref = idx
+    rng = np.random.default_rng(7)
+    p = np.zeros(512, dtype=np.float32)
+    p[:mlp.N_USED] = rng.normal(0, 0.6, mlp.N_USED)
+    p[320:384] = np.abs(p[320:384])  # b1 > 0: units active on non-negative features
+    w = mlp.float_to_bf16_bits(p)
+    table = oracle.knn_graph(ref, docs, 8, 10, 0.8)
+    ix.set_knn(table)
+    _log(f"[knn+probe parity] tau={tau} query_mass={qmass} cut={cut}")
+    r = ref.pruned_search(qs, 10, cut, 0.8, c_cap=cut, probe=w, tau=tau, knn=table, query_mass=qmass)
+    ids, sc, pref, cnt, hmin, term = ix.search(to_device_csr(qs), 10, cut, 0.8, trace=True, prefix_stride=cut,
+                                               probe=P.to_device(w), probe_tau=tau, refine=True,
+                                               query_mass=qmass)
+    assert not compare_with_oracle((ids, sc, pref, cnt), r, 10, cut)
+    assert np.array_equal(hmin.cpu().numpy(), r["hmin"])
+    assert (r["hmin"] >= 0).any()
 
 
 def test_refinement_inside_graph_replays(idx):
