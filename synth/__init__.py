@@ -51,6 +51,10 @@ def _load():
                                    ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
         lib.synth_fill.restype = ctypes.c_int
+        lib.synth_counts_range.argtypes = [ctypes.c_uint64] + lib.synth_counts.argtypes
+        lib.synth_counts_range.restype = ctypes.c_int
+        lib.synth_fill_range.argtypes = [ctypes.c_uint64] + lib.synth_fill.argtypes
+        lib.synth_fill_range.restype = ctypes.c_int
         lib.synth_philox4x32_10.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.synth_half_from_double.argtypes = [ctypes.c_double]
         lib.synth_half_from_double.restype = ctypes.c_uint16
@@ -103,21 +107,23 @@ class CSR:
 
 def generate(n_rows: int, *, seed: int = 0, stream: int = STREAM_DOCS, law: str = "poisson",
              mean: float = 120.0, lo: int = 10, hi: int = 400, dim: int = DIM,
-             zipf_s: float = ZIPF_S, sigma: float = SIGMA) -> CSR:
-    """Generate ``n_rows`` sparse rows.  ``law`` is "poisson" (mean, clipped to
+             zipf_s: float = ZIPF_S, sigma: float = SIGMA, row0: int = 0) -> CSR:
+    """Generate ``n_rows`` sparse rows (rows row0 .. row0 + n_rows - 1 of the
+    stream: every row depends only on (seed, stream, row), so slices
+    concatenate to the whole).  ``law`` is "poisson" (mean, clipped to
     [lo, hi]) or "uniform" (integer in [lo, hi])."""
     lib = _load()
     law_id = {"poisson": 0, "uniform": 1}[law]
     counts = np.empty(n_rows, dtype=np.uint32)
-    rc = lib.synth_counts(n_rows, dim, zipf_s, law_id, mean, lo, hi, seed, stream,
-                          counts.ctypes.data_as(ctypes.c_void_p))
+    rc = lib.synth_counts_range(row0, n_rows, dim, zipf_s, law_id, mean, lo, hi, seed, stream,
+                                counts.ctypes.data_as(ctypes.c_void_p))
     if rc != 0:
         raise ValueError(f"synth_counts failed ({rc})")
     row_ptr = np.zeros(n_rows + 1, dtype=np.uint64)
     np.cumsum(counts, out=row_ptr[1:])
     words = np.empty(int(row_ptr[-1]), dtype=np.uint32)
-    rc = lib.synth_fill(n_rows, dim, zipf_s, law_id, mean, lo, hi, sigma, seed, stream,
-                        row_ptr.ctypes.data_as(ctypes.c_void_p), words.ctypes.data_as(ctypes.c_void_p))
+    rc = lib.synth_fill_range(row0, n_rows, dim, zipf_s, law_id, mean, lo, hi, sigma, seed, stream,
+                              row_ptr.ctypes.data_as(ctypes.c_void_p), words.ctypes.data_as(ctypes.c_void_p))
     if rc != 0:
         raise ValueError(f"synth_fill failed ({rc})")
     return CSR(row_ptr, words, dim)

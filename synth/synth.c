@@ -83,31 +83,58 @@ static double rng_unif(rng_t* g) {
     return ((double)a * 67108864.0 + (double)b) * (1.0 / 9007199254740992.0);
 }
 
-/* IEEE binary16 from double, round to nearest even; input finite, >= 0 */
+/* IEEE binary16 from double, round to nearest even; input finite, >= 0.
+ * Works on the double's bit fields: the 52-bit fraction is cut to 10 bits
+ * (normal results) or to a multiple of 2^-24 (subnormal results), and the
+ * discarded bits decide the rounding, ties to the even result. */
 uint16_t synth_half_from_double(double x) {
     if (!(x > 0.0)) return 0;
     if (x >= 65520.0) return 0x7C00; /* overflow to +inf */
-    int e;
-    double m = frexp(x, &e); /* x = m * 2^e, m in [0.5, 1) */
-    int exp_h = e - 1;       /* x = (2m) * 2^(e-1), 2m in [1, 2) */
-    if (exp_h < -14) {
-        /* subnormal: value = k * 2^-24 */
-        double k = ldexp(x, 24);
-        double r = nearbyint(k); /* default rounding mode: nearest even */
-        return (uint16_t)r;      /* r == 1024 rolls into the smallest normal */
+    uint64_t b;
+    memcpy(&b, &x, sizeof b);
+    const int e = (int)((b >> 52) & 0x7FF) - 1023; /* x = 1.f * 2^e (x is a normal double here) */
+    const uint64_t sig = (b & 0xFFFFFFFFFFFFFull) | (1ull << 52); /* 53-bit significand */
+    int shift;      /* bits of sig below the kept unit */
+    uint32_t base;  /* exponent field of the result before rounding */
+    if (e >= -14) {
+        shift = 42;
+        base = (uint32_t)(e + 15);
+    } else {
+        /* subnormal: units of 2^-24, i.e. sig >> (52 - (e + 24)) */
+        shift = 52 - (e + 24);
+        base = 0;
+        if (shift > 63) return 0; /* below 2^-25 rounds to zero */
     }
-    double frac = ldexp(2.0 * m - 1.0, 10); /* 10 fraction bits */
-    double r = nearbyint(frac);
-    uint32_t mant = (uint32_t)r;
-    uint32_t biased = (uint32_t)(exp_h + 15);
+    uint64_t kept = sig >> shift;
+    const uint64_t rem = sig & ((1ull << shift) - 1), half = 1ull << (shift - 1);
+    if (rem > half || (rem == half && (kept & 1))) ++kept;
+    if (base == 0) return (uint16_t)kept; /* 1024 rolls into the smallest normal */
+    /* kept in [1024, 2048]: implicit bit plus 10 fraction bits */
+    uint32_t biased = base, mant = (uint32_t)kept - 1024;
     if (mant == 1024) { mant = 0; biased++; }
     if (biased >= 31) return 0x7C00;
     return (uint16_t)((biased << 10) | mant);
 }
 
+/* Ascending sort of n distinct 16-bit ids: two stable byte passes. */
+static void sort_u16(uint16_t* a, int n, uint16_t* tmp) {
+    int cnt[257];
+    for (int pass = 0; pass < 2; ++pass) {
+        const int sh = 8 * pass;
+        memset(cnt, 0, sizeof cnt);
+        for (int i = 0; i < n; ++i) cnt[((a[i] >> sh) & 0xFF) + 1]++;
+        for (int i = 0; i < 256; ++i) cnt[i + 1] += cnt[i];
+        for (int i = 0; i < n; ++i) tmp[cnt[(a[i] >> sh) & 0xFF]++] = a[i];
+        memcpy(a, tmp, sizeof(uint16_t) * (size_t)n);
+    }
+}
+
+#define GUIDE_N 65536
+
 typedef struct {
     int dim;
     double* zipf_cdf; /* cdf[r-1] = P(rank <= r) */
+    int* zipf_guide;  /* guide[k] = smallest index with cdf > k / GUIDE_N (k <= GUIDE_N) */
     int law;          /* 0 = Poisson(mean) clipped, 1 = uniform integer */
     int lo, hi;
     int pois_n;       /* table length */
@@ -138,9 +165,13 @@ static int draw_count(const law_t* L, rng_t* g) {
     return n;
 }
 
+/* Inversion of the Zipf cdf: the smallest index with cdf > u.  The guide
+ * table narrows the search to [guide[k], guide[k + 1]] for u in
+ * [k / GUIDE_N, (k + 1) / GUIDE_N); the result is the plain binary search's. */
 static int draw_rank0(const law_t* L, rng_t* g) {
     double u = rng_unif(g);
-    int a = 0, b = L->dim - 1;
+    const int k = (int)(u * (double)GUIDE_N);
+    int a = L->zipf_guide[k], b = L->zipf_guide[k + 1];
     while (a < b) {
         int mid = (a + b) >> 1;
         if (L->zipf_cdf[mid] > u) b = mid; else a = mid + 1;
@@ -158,14 +189,10 @@ static double draw_value(const law_t* L, rng_t* g) {
     return v;
 }
 
-static int cmp_u16(const void* a, const void* b) {
-    int x = *(const uint16_t*)a, y = *(const uint16_t*)b;
-    return (x > y) - (x < y);
-}
-
 static int law_setup(law_t* L, int dim, double zipf_s, int law, double mean, int lo, int hi, double sigma) {
     L->dim = dim; L->law = law; L->lo = lo; L->hi = hi; L->sigma = sigma;
     L->zipf_cdf = (double*)malloc(sizeof(double) * (size_t)dim);
+    L->zipf_guide = NULL;
     L->pois_cdf = NULL; L->pois_n = 0;
     if (!L->zipf_cdf) return -1;
     double tot = 0.0;
@@ -173,6 +200,13 @@ static int law_setup(law_t* L, int dim, double zipf_s, int law, double mean, int
     double c = 0.0;
     for (int r = 1; r <= dim; ++r) { c += pow((double)r, -zipf_s) / tot; L->zipf_cdf[r - 1] = c; }
     L->zipf_cdf[dim - 1] = 1.0;
+    L->zipf_guide = (int*)malloc(sizeof(int) * (GUIDE_N + 1));
+    if (!L->zipf_guide) return -1;
+    for (int k = 0, a = 0; k <= GUIDE_N; ++k) {
+        const double u = (double)k / (double)GUIDE_N;
+        while (a < dim - 1 && !(L->zipf_cdf[a] > u)) ++a;
+        L->zipf_guide[k] = a;
+    }
     if (law == 0) {
         int n = hi + 1;
         L->pois_n = n;
@@ -189,27 +223,33 @@ static int law_setup(law_t* L, int dim, double zipf_s, int law, double mean, int
     return 0;
 }
 
-static void law_free(law_t* L) { free(L->zipf_cdf); free(L->pois_cdf); }
+static void law_free(law_t* L) { free(L->zipf_cdf); free(L->zipf_guide); free(L->pois_cdf); }
 
-/* Pass 1: number of nonzeros of every row. */
-int synth_counts(uint64_t n_rows, int dim, double zipf_s, int law, double mean, int lo, int hi,
-                 uint64_t seed, uint32_t stream, uint32_t* counts) {
+/* Pass 1: number of nonzeros of rows row0 .. row0 + n_rows - 1. */
+int synth_counts_range(uint64_t row0, uint64_t n_rows, int dim, double zipf_s, int law, double mean, int lo,
+                       int hi, uint64_t seed, uint32_t stream, uint32_t* counts) {
     law_t L;
     if (dim < 1 || dim > 65536 || lo < 1 || hi < lo || hi > dim) return -1;
     if (law_setup(&L, dim, zipf_s, law, mean, lo, hi, 0.6) != 0) return -1;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < (int64_t)n_rows; ++i) {
         rng_t g;
-        rng_init(&g, seed, stream, (uint64_t)i);
+        rng_init(&g, seed, stream, row0 + (uint64_t)i);
         counts[i] = (uint32_t)draw_count(&L, &g);
     }
     law_free(&L);
     return 0;
 }
 
-/* Pass 2: fill rows; row_ptr must already hold the prefix sums of counts. */
-int synth_fill(uint64_t n_rows, int dim, double zipf_s, int law, double mean, int lo, int hi, double sigma,
-               uint64_t seed, uint32_t stream, const uint64_t* row_ptr, uint32_t* words) {
+int synth_counts(uint64_t n_rows, int dim, double zipf_s, int law, double mean, int lo, int hi,
+                 uint64_t seed, uint32_t stream, uint32_t* counts) {
+    return synth_counts_range(0, n_rows, dim, zipf_s, law, mean, lo, hi, seed, stream, counts);
+}
+
+/* Pass 2: fill rows row0 .. row0 + n_rows - 1; row_ptr (n_rows + 1 entries,
+ * relative to words) must already hold the prefix sums of their counts. */
+int synth_fill_range(uint64_t row0, uint64_t n_rows, int dim, double zipf_s, int law, double mean, int lo, int hi,
+                     double sigma, uint64_t seed, uint32_t stream, const uint64_t* row_ptr, uint32_t* words) {
     law_t L;
     if (dim < 1 || dim > 65536 || lo < 1 || hi < lo || hi > dim) return -1;
     if (law_setup(&L, dim, zipf_s, law, mean, lo, hi, sigma) != 0) return -1;
@@ -218,14 +258,15 @@ int synth_fill(uint64_t n_rows, int dim, double zipf_s, int law, double mean, in
     {
         uint8_t* seen = (uint8_t*)calloc((size_t)dim, 1);
         uint16_t* ids = (uint16_t*)malloc(sizeof(uint16_t) * (size_t)(hi + 1));
-        if (!seen || !ids) {
+        uint16_t* tmp = (uint16_t*)malloc(sizeof(uint16_t) * (size_t)(hi + 1));
+        if (!seen || !ids || !tmp) {
 #pragma omp atomic write
             err = 1;
         } else {
 #pragma omp for schedule(static)
             for (int64_t i = 0; i < (int64_t)n_rows; ++i) {
                 rng_t g;
-                rng_init(&g, seed, stream, (uint64_t)i);
+                rng_init(&g, seed, stream, row0 + (uint64_t)i);
                 int n = draw_count(&L, &g);
                 if ((uint64_t)n != row_ptr[i + 1] - row_ptr[i]) {
 #pragma omp atomic write
@@ -237,7 +278,7 @@ int synth_fill(uint64_t n_rows, int dim, double zipf_s, int law, double mean, in
                     int t = draw_rank0(&L, &g);
                     if (!seen[t]) { seen[t] = 1; ids[got++] = (uint16_t)t; }
                 }
-                qsort(ids, (size_t)n, sizeof(uint16_t), cmp_u16);
+                sort_u16(ids, n, tmp);
                 uint32_t* w = words + row_ptr[i];
                 for (int j = 0; j < n; ++j) {
                     seen[ids[j]] = 0;
@@ -248,7 +289,13 @@ int synth_fill(uint64_t n_rows, int dim, double zipf_s, int law, double mean, in
         }
         free(seen);
         free(ids);
+        free(tmp);
     }
     law_free(&L);
     return err ? -err : 0;
+}
+
+int synth_fill(uint64_t n_rows, int dim, double zipf_s, int law, double mean, int lo, int hi, double sigma,
+               uint64_t seed, uint32_t stream, const uint64_t* row_ptr, uint32_t* words) {
+    return synth_fill_range(0, n_rows, dim, zipf_s, law, mean, lo, hi, sigma, seed, stream, row_ptr, words);
 }
