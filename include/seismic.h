@@ -158,17 +158,35 @@ const char* seismic_last_error(void);
    parameters, ENOMEM on allocation failure. */
 int seismic_build_index(const seismic_csr* docs, const seismic_build_params* params, seismic_index** out);
 
-/* The same build with the per-list work (Set alpha-MSS selection, centroid
-   sampling, K-means assignment, blocks, gamma-MSS summaries, quantization)
-   on HIP device `device`; the inverted lists are formed on the host.  For
-   values in [2^-6, 2^6] every inner product of the assignment is exact, so
-   the index is byte for byte the host build's.  Lists beyond the GPU path's
-   capacities (more than 1024 blocks in a list, more than 2048 entries tied
-   at a summary's mass boundary, more than 4096 entries in one summary) make
-   it fall back to seismic_build_index.  Synchronous; the index is returned
-   in host memory like seismic_build_index's (upload it to search). */
+/* The same build (Algorithm "Indexing with Seismic", Section 4.4) with
+   everything after input validation on HIP device `device`: the column
+   lists (inverted lists before truncation) by a stable counting transpose,
+   and per list the Set alpha-MSS selection, centroid sampling, K-means
+   assignment, blocks, gamma-MSS summaries and quantization.  For values in
+   [2^-6, 2^6] every inner product of the assignment is exact, so the index
+   is byte for byte the host build's.  Lists beyond the GPU path's
+   capacities (more than 1024 blocks or 2^24 kept postings in one list)
+   make it fall back to seismic_build_index.  Synchronous; host documents
+   (on_device = 0); the index is returned in host memory like
+   seismic_build_index's (upload it to search). */
 int seismic_build_index_gpu(const seismic_csr* docs, const seismic_build_params* params, int device,
                             seismic_index** out);
+
+/* The same build for a collection already in the memory of HIP device
+   `device` (on_device = 1; rows are validated on the device as for the host
+   build), and the index stays there: the result is resident on `device`
+   with the plain row layout (as after seismic_index_upload with flags 0),
+   ready to search, and holds no host copy of the forward index, postings or
+   summaries, so a collection that fits the device but not host memory can
+   be indexed.  The documents are copied into the index; the caller may free
+   them once the call returns.  Device memory at the peak: the documents,
+   6 bytes per nonzero of column lists, and the kept lists and summaries.
+   serialize/save copy the index back to the host; upload returns ESTATE.
+   The same results as seismic_build_index_gpu, byte for byte.  Lists
+   beyond the capacities above return EINVAL (no host fallback); ENOMEM
+   when device memory runs out.  Synchronous. */
+int seismic_build_index_device(const seismic_csr* docs, const seismic_build_params* params, int device,
+                               seismic_index** out);
 
 /* Serialized form (format version 1, little-endian): see DESIGN notes in
    the source.  save writes a file; serialize writes into a caller buffer of

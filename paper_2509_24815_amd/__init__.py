@@ -33,6 +33,13 @@ class Index:
                                                    n_threads, int(verbose), alpha, device))
 
     @classmethod
+    def build_device(cls, docs, lam: int, beta: int, gamma: float, seed: int = 0, verbose: bool = False,
+                     alpha: float = 0.0, device: int = 0) -> "Index":
+        """The same index built from documents already on the device
+        (binding.device_csr), left resident there (plain row layout)."""
+        return cls(binding.seismic_build_index_device(docs, lam, beta, gamma, seed, 0, int(verbose), alpha, device))
+
+    @classmethod
     def load(cls, path: str) -> "Index":
         return cls(binding.seismic_index_load(path))
 

@@ -95,6 +95,7 @@ def load():
         "seismic_last_error": ([], ctypes.c_char_p),
         "seismic_build_index": ([P(Csr), P(BuildParams), P(vp)], i32),
         "seismic_build_index_gpu": ([P(Csr), P(BuildParams), i32, P(vp)], i32),
+        "seismic_build_index_device": ([P(Csr), P(BuildParams), i32, P(vp)], i32),
         "seismic_index_serialized_size": ([vp, P(u64)], i32),
         "seismic_index_serialize": ([vp, vp, u64], i32),
         "seismic_index_save": ([vp, ctypes.c_char_p], i32),
@@ -191,6 +192,16 @@ def seismic_build_index_gpu(row_ptr, words, dim, lam, beta, gamma, seed=0, n_thr
     p = BuildParams(lam, beta, gamma, seed, n_threads, verbose, alpha)
     h = ctypes.c_void_p()
     _check(lib.seismic_build_index_gpu(ctypes.byref(csr), ctypes.byref(p), device, ctypes.byref(h)))
+    return h.value
+
+
+def seismic_build_index_device(csr: "Csr", lam, beta, gamma, seed=0, n_threads=0, verbose=0, alpha=0.0,
+                               device=0) -> int:
+    """csr: a device_csr of the documents; the index is built and stays on the device."""
+    lib = load()
+    p = BuildParams(lam, beta, gamma, seed, n_threads, verbose, alpha)
+    h = ctypes.c_void_p()
+    _check(lib.seismic_build_index_device(ctypes.byref(csr), ctypes.byref(p), device, ctypes.byref(h)))
     return h.value
 
 

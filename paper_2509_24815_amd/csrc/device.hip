@@ -233,6 +233,62 @@ int build_block_rows(DeviceIndex* d, const HostIndex& h) {
 
 }  // namespace
 
+namespace seismic {
+
+int download_host_index(const seismic_index* ix, HostIndex& out) {
+    const HostIndex& h = ix->h;
+    const DeviceIndex* d = ix->dev;
+    if (!d) return fail(SEISMIC_ESTATE, "download: index is not on a device");
+    DeviceGuard g(d->device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "download: cannot select device %d", d->device);
+    out = HostIndex();
+    out.dim = h.dim;
+    out.n_docs = h.n_docs;
+    out.lambda = h.lambda;
+    out.beta = h.beta;
+    out.gamma = h.gamma;
+    out.seed = h.seed;
+    out.alpha = h.alpha;
+    out.list_off = h.list_off;
+    out.blk_post_off = h.blk_post_off;
+    out.blk_sum_off = h.blk_sum_off;
+    out.blk_m = h.blk_m;
+    out.blk_delta = h.blk_delta;
+    out.blk_centroid = h.blk_centroid;
+    out.row_ptr.resize(h.n_docs + 1);
+    out.words.resize(ix->dev_nnz);
+    out.postings.resize(ix->dev_postings);
+    out.sum_term.resize(ix->dev_sums);
+    out.sum_code.resize(ix->dev_sums);
+    const seismic_dev::DevIdx& v = d->view;
+    HIP_TRY(hipMemcpy(out.row_ptr.data(), v.row_ptr, out.row_ptr.size() * 8, hipMemcpyDeviceToHost));
+    if (!out.words.empty()) HIP_TRY(hipMemcpy(out.words.data(), v.words, out.words.size() * 4, hipMemcpyDeviceToHost));
+    if (!out.postings.empty())
+        HIP_TRY(hipMemcpy(out.postings.data(), v.postings, out.postings.size() * 4, hipMemcpyDeviceToHost));
+    if (!out.sum_term.empty()) {
+        HIP_TRY(hipMemcpy(out.sum_term.data(), v.sum_term, out.sum_term.size() * 2, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(out.sum_code.data(), v.sum_code, out.sum_code.size(), hipMemcpyDeviceToHost));
+    }
+    return SEISMIC_OK;
+}
+
+int full_host_index(const seismic_index* ix, HostIndex& tmp, const HostIndex** out) {
+    if (!ix->device_only) {
+        *out = &ix->h;
+        return SEISMIC_OK;
+    }
+    int rc;
+    try {
+        rc = download_host_index(ix, tmp);
+    } catch (const std::bad_alloc&) {
+        rc = fail(SEISMIC_ENOMEM, "download: host allocation failed");
+    }
+    if (!rc) *out = &tmp;
+    return rc;
+}
+
+}  // namespace seismic
+
 extern "C" {
 
 int seismic_index_upload(seismic_index* index, int device, uint32_t flags) {
@@ -572,7 +628,7 @@ int seismic_knn_build(seismic_index* index, uint32_t kappa, uint32_t query_cut, 
     for (uint64_t s = 0; s < n && !rc; s += chunk) {
         const uint32_t m = (uint32_t)std::min<uint64_t>(chunk, n - s);
         // documents [s, s + m) of the resident forward index as the queries
-        seismic_csr q{m, index->h.nnz(), index->h.dim, 1, d->view.row_ptr + s, d->view.words};
+        seismic_csr q{m, index->nnz(), index->h.dim, 1, d->view.row_ptr + s, d->view.words};
         rc = seismic_search_batch(index, ws, &q, &sp, ids, sc, nullptr, nullptr);
         if (!rc) {
             hipLaunchKernelGGL(k_knn_finalize, dim3((m + 255) / 256), dim3(256), 0, nullptr, ids, m, (uint32_t)s, kappa,
@@ -610,26 +666,13 @@ int exact_topk(const seismic_index* index_c, const seismic_csr* queries, uint32_
     std::lock_guard<std::mutex> lk(index->mu);
     hipStream_t st = (hipStream_t)stream;
     if (!d->csc_off) {
-        const HostIndex& h = index->h;
-        HostCSC csc;
-        try {
-            build_csc(h.row_ptr.data(), h.words.data(), h.n_docs, h.dim, 0, csc);
-        } catch (const std::bad_alloc&) {
-            return fail(SEISMIC_ENOMEM, "exact_topk: host allocation failed");
-        }
-        hipError_t e1 = hipMalloc((void**)&d->csc_off, csc.off.size() * 8);
-        hipError_t e2 = hipMalloc((void**)&d->csc_doc, std::max<size_t>(csc.doc.size() * 4, 16));
-        hipError_t e3 = hipMalloc((void**)&d->csc_val, std::max<size_t>(csc.val.size() * 2, 16));
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-            (void)hipFree(d->csc_off); (void)hipFree(d->csc_doc); (void)hipFree(d->csc_val);
-            d->csc_off = nullptr; d->csc_doc = nullptr; d->csc_val = nullptr;
-            return fail(SEISMIC_ENOMEM, "exact_topk: device allocation of the inverted index failed");
-        }
-        HIP_TRY(hipMemcpy(d->csc_off, csc.off.data(), csc.off.size() * 8, hipMemcpyHostToDevice));
-        if (!csc.doc.empty()) {
-            HIP_TRY(hipMemcpy(d->csc_doc, csc.doc.data(), csc.doc.size() * 4, hipMemcpyHostToDevice));
-            HIP_TRY(hipMemcpy(d->csc_val, csc.val.data(), csc.val.size() * 2, hipMemcpyHostToDevice));
-        }
+        // column lists of the resident forward index, built on the device
+        seismic_dev::DevCsc csc;
+        int rc = seismic_dev::device_csc(d->view.row_ptr, d->view.words, index->h.n_docs, index->h.dim, csc, nullptr);
+        if (rc) return rc;
+        d->csc_off = csc.off;
+        d->csc_doc = csc.doc;
+        d->csc_val = csc.val;
     }
     const uint64_t* q_ptr = queries->row_ptr;
     const uint32_t* q_words = queries->words;

@@ -52,3 +52,34 @@ class DeviceGuard {
 
 // Grows a device buffer to at least need elements (contents are dropped).
 int grow(void** p, size_t& cap, size_t need, size_t elem);
+
+namespace seismic_dev {
+
+// Column lists of a device-resident collection: postings of term t are
+// [off[t], off[t+1]) with document ids (doc) and fp16 values (val), document
+// ascending.  Device memory owned by the holder.
+struct DevCsc {
+    uint64_t* off = nullptr;
+    uint32_t* doc = nullptr;
+    uint16_t* val = nullptr;
+    void release() {
+        (void)hipFree(off);
+        (void)hipFree(doc);
+        (void)hipFree(val);
+        off = nullptr;
+        doc = nullptr;
+        val = nullptr;
+    }
+};
+
+// Builds the column lists of n_docs device rows (dim terms) on the current
+// device (synchronous).  host_off, if given, receives off.  The rows must be
+// valid (validate_csr_device).
+int device_csc(const uint64_t* row_ptr, const uint32_t* words, uint64_t n_docs, uint32_t dim, DevCsc& out,
+               std::vector<uint64_t>* host_off);
+
+// Checks device-resident rows on the current device as validate_csr_host
+// does for host rows; row_max (may be NULL) receives the longest row.
+int validate_csr_device(const seismic_csr* m, uint32_t max_len, const char* what, uint32_t* row_max);
+
+}  // namespace seismic_dev

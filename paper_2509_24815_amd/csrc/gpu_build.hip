@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 
 #include "device_internal.h"
@@ -512,6 +513,10 @@ __global__ __launch_bounds__(kBT) void k_build_terms(BuildArgs a) {
 
 namespace {
 
+using seismic_dev::BuildArgs;
+using seismic_dev::DevCsc;
+using seismic_dev::kWave;
+
 template <typename T>
 int dalloc(std::vector<void*>& keep, T*& p, size_t n) {
     p = nullptr;
@@ -530,106 +535,87 @@ int dupload(std::vector<void*>& keep, T*& p, const T* src, size_t n) {
     return SEISMIC_OK;
 }
 
+// Device buffers of one build; freed at scope exit unless taken.
 struct Frees {
     std::vector<void*> p;
+    void drop(void* x) {
+        auto it = std::find(p.begin(), p.end(), x);
+        if (it != p.end()) { (void)hipFree(x); p.erase(it); }
+    }
+    void take(void* x) {
+        auto it = std::find(p.begin(), p.end(), x);
+        if (it != p.end()) p.erase(it);
+    }
     ~Frees() {
         for (void* x : p) (void)hipFree(x);
     }
 };
 
-}  // namespace
+// Per-term plan from the full list lengths: kept count (the list cap of
+// Set alpha-MSS), block count (proportional to the kept count, at least
+// one), offsets of the term's postings and block slots, and the work order
+// (longest lists first).
+struct Plan {
+    std::vector<uint32_t> t_n, t_nb, order;
+    std::vector<uint64_t> t_post, t_bcap;
+    uint32_t n_max = 1, nb_max = 1;
+    uint64_t total_n = 0, total_b = 0;
+};
 
-extern "C" int seismic_build_index_gpu(const seismic_csr* docs, const seismic_build_params* p, int device,
-                                       seismic_index** out) {
-    using namespace seismic_dev;
-    if (!out || !p || !docs) return fail(SEISMIC_EINVAL, "gpu build: null argument");
-    *out = nullptr;
-    if (p->lambda < 1) return fail(SEISMIC_EINVAL, "build: lambda must be >= 1");
-    if (p->beta < 1) return fail(SEISMIC_EINVAL, "build: beta must be >= 1");
-    if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return fail(SEISMIC_EINVAL, "build: gamma must be in (0, 1]");
-    if (!(p->alpha >= 0.0 && p->alpha <= 1.0)) return fail(SEISMIC_EINVAL, "build: alpha must be in [0, 1]");
-    int rc = validate_csr_host(docs, 65536, "build: docs");
-    if (rc) return rc;
-    if (docs->n_rows >= 0xFFFFFFFFull) return fail(SEISMIC_EINVAL, "build: more than 2^32-1 documents");
-    DeviceGuard g(device);
-    if (!g.ok()) return fail(SEISMIC_EHIP, "gpu build: cannot select device %d", device);
-    auto t_start = std::chrono::steady_clock::now();
-    auto elapsed = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
-    seismic_index* ix = new (std::nothrow) seismic_index();
-    if (!ix) return fail(SEISMIC_ENOMEM, "gpu build: host allocation failed");
-    HostIndex& H = ix->h;
-    const uint32_t dim = docs->dim;
-    const int nthreads = resolve_threads(p->n_threads);
-    try {
-        H.dim = dim;
-        H.n_docs = docs->n_rows;
-        H.lambda = p->lambda;
-        H.beta = p->beta;
-        H.gamma = p->gamma;
-        H.seed = p->seed;
-        H.alpha = p->alpha;
-        H.row_ptr.assign(docs->row_ptr, docs->row_ptr + docs->n_rows + 1);
-        H.words.assign(docs->words, docs->words + docs->nnz);
-    } catch (const std::bad_alloc&) {
-        delete ix;
-        return fail(SEISMIC_ENOMEM, "gpu build: host allocation failed");
-    }
-    HostCSC csc;
-    build_csc(H.row_ptr.data(), H.words.data(), H.n_docs, dim, nthreads, csc);
-    // per term: kept count, block count, offsets
-    std::vector<uint32_t> t_n(dim), t_nb(dim), order;
-    std::vector<uint64_t> t_post(dim + 1, 0), t_bcap(dim + 1, 0);
-    uint32_t n_max = 1, nb_max = 1, row_max = 1;
-    for (uint64_t d = 0; d < H.n_docs; ++d) row_max = std::max<uint32_t>(row_max, (uint32_t)(H.row_ptr[d + 1] - H.row_ptr[d]));
+void plan_terms(const std::vector<uint64_t>& off, uint32_t dim, const seismic_build_params* p, Plan& P) {
+    P.t_n.assign(dim, 0);
+    P.t_nb.assign(dim, 0);
+    P.t_post.assign(dim + 1, 0);
+    P.t_bcap.assign(dim + 1, 0);
+    P.order.clear();
     for (uint32_t t = 0; t < dim; ++t) {
-        const uint64_t nf = csc.off[t + 1] - csc.off[t];
+        const uint64_t nf = off[t + 1] - off[t];
         uint64_t n = std::min<uint64_t>(nf, list_cap(nf, p->lambda, p->alpha));
         uint64_t nb = 0;
         if (n) {
             nb = ((uint64_t)p->beta * n + p->lambda - 1) / p->lambda;
             nb = std::max<uint64_t>(1, std::min<uint64_t>(nb, n));
-            order.push_back(t);
+            P.order.push_back(t);
         }
-        t_n[t] = (uint32_t)n;
-        t_nb[t] = (uint32_t)nb;
-        t_post[t + 1] = t_post[t] + n;
-        t_bcap[t + 1] = t_bcap[t] + nb;
-        n_max = std::max<uint32_t>(n_max, (uint32_t)n);
-        nb_max = std::max<uint32_t>(nb_max, (uint32_t)nb);
+        P.t_n[t] = (uint32_t)std::min<uint64_t>(n, 0xFFFFFFFFull);
+        P.t_nb[t] = (uint32_t)std::min<uint64_t>(nb, 0xFFFFFFFFull);
+        P.t_post[t + 1] = P.t_post[t] + n;
+        P.t_bcap[t + 1] = P.t_bcap[t] + nb;
+        P.n_max = (uint32_t)std::max<uint64_t>(P.n_max, std::min<uint64_t>(n, 0xFFFFFFFFull));
+        P.nb_max = (uint32_t)std::max<uint64_t>(P.nb_max, std::min<uint64_t>(nb, 0xFFFFFFFFull));
     }
-    if (nb_max > kMaxNb || n_max > (1u << 24)) {
-        delete ix;
-        if (p->verbose) std::fprintf(stderr, "gpu build: lists beyond the GPU path's limits; building on the host\n");
-        return seismic_build_index(docs, p, out);
-    }
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return t_n[x] > t_n[y]; });
-    if (p->verbose) std::fprintf(stderr, "gpu build: inverted lists on the host (%.1f s)\n", elapsed());
+    std::stable_sort(P.order.begin(), P.order.end(), [&](uint32_t x, uint32_t y) { return P.t_n[x] > P.t_n[y]; });
+    P.total_n = P.t_post[dim];
+    P.total_b = P.t_bcap[dim];
+}
+
+bool plan_fits(const Plan& P) { return P.nb_max <= seismic_dev::kMaxNb && P.n_max <= (1u << 24); }
+
+// Runs the per-term kernel over device rows d_rp/d_w and their column lists.
+// On return (SEISMIC_OK) a holds the device outputs (owned by F) and flags
+// the kernel's flags (0: complete).
+int run_terms(const uint64_t* d_rp, const uint32_t* d_w, uint32_t dim, uint32_t row_max, const DevCsc& csc,
+              const Plan& P, const seismic_build_params* p, int device, Frees& F, BuildArgs& a, uint32_t& flags,
+              uint64_t*& d_bsat) {
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ix; return fail(SEISMIC_EHIP, "gpu build: device query failed"); }
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(SEISMIC_EHIP, "gpu build: device query failed");
     const uint32_t grid = (uint32_t)std::max(1, prop.multiProcessorCount) * 2;
-    const uint64_t total_n = t_post[dim], total_b = t_bcap[dim];
-    const uint64_t ecap = (uint64_t)nb_max * row_max;
-    const uint64_t sum_cap = std::min<uint64_t>(std::max<uint64_t>(total_b * 256, 1 << 20), 4000000000ull);
-    Frees F;
-    BuildArgs a{};
-    uint64_t *d_rp = nullptr, *d_coff = nullptr, *d_tpost = nullptr, *d_tbcap = nullptr, *d_bsat = nullptr;
-    uint32_t *d_w = nullptr, *d_cdoc = nullptr, *d_order = nullptr, *d_tn = nullptr, *d_tnb = nullptr, *d_q = nullptr;
-    uint16_t* d_cval = nullptr;
-    rc = SEISMIC_OK;
-    if (!rc) rc = dupload(F.p, d_rp, H.row_ptr.data(), H.row_ptr.size());
-    if (!rc) rc = dupload(F.p, d_w, H.words.data(), H.words.size());
-    if (!rc) rc = dupload(F.p, d_coff, csc.off.data(), csc.off.size());
-    if (!rc) rc = dupload(F.p, d_cdoc, csc.doc.data(), csc.doc.size());
-    if (!rc) rc = dupload(F.p, d_cval, csc.val.data(), csc.val.size());
-    if (!rc) rc = dupload(F.p, d_order, order.data(), order.size());
-    if (!rc) rc = dupload(F.p, d_tn, t_n.data(), t_n.size());
-    if (!rc) rc = dupload(F.p, d_tnb, t_nb.data(), t_nb.size());
-    if (!rc) rc = dupload(F.p, d_tpost, t_post.data(), t_post.size());
-    if (!rc) rc = dupload(F.p, d_tbcap, t_bcap.data(), t_bcap.size());
+    const uint64_t ecap = (uint64_t)P.nb_max * std::max<uint32_t>(row_max, 1);
+    const uint64_t sum_cap = std::min<uint64_t>(std::max<uint64_t>(P.total_b * 256, 1 << 20), 4000000000ull);
+    uint32_t *d_order = nullptr, *d_tn = nullptr, *d_tnb = nullptr, *d_q = nullptr;
+    uint64_t *d_tpost = nullptr, *d_tbcap = nullptr;
+    a = BuildArgs{};
+    int rc = SEISMIC_OK;
+    if (!rc) rc = dupload(F.p, d_order, P.order.data(), P.order.size());
+    if (!rc) rc = dupload(F.p, d_tn, P.t_n.data(), P.t_n.size());
+    if (!rc) rc = dupload(F.p, d_tnb, P.t_nb.data(), P.t_nb.size());
+    if (!rc) rc = dupload(F.p, d_tpost, P.t_post.data(), P.t_post.size());
+    if (!rc) rc = dupload(F.p, d_tbcap, P.t_bcap.data(), P.t_bcap.size());
     if (!rc) rc = dalloc(F.p, d_q, 4);
-    a.row_ptr = d_rp; a.words = d_w; a.dim = dim; a.csc_off = d_coff; a.csc_doc = d_cdoc; a.csc_val = d_cval;
-    a.order = d_order; a.n_work = (uint32_t)order.size(); a.t_n = d_tn; a.t_nb = d_tnb; a.t_post = d_tpost;
+    a.row_ptr = d_rp; a.words = d_w; a.dim = dim; a.csc_off = csc.off; a.csc_doc = csc.doc; a.csc_val = csc.val;
+    a.order = d_order; a.n_work = (uint32_t)P.order.size(); a.t_n = d_tn; a.t_nb = d_tnb; a.t_post = d_tpost;
     a.t_bcap = d_tbcap; a.queue = d_q; a.seed = p->seed; a.gamma = p->gamma; a.sum_cap = sum_cap;
+    const uint64_t total_n = P.total_n, total_b = P.total_b;
     if (!rc) rc = dalloc(F.p, a.list_docs, total_n);
     if (!rc) rc = dalloc(F.p, a.postings, total_n);
     if (!rc) rc = dalloc(F.p, a.t_nblk, dim);
@@ -644,10 +630,10 @@ extern "C" int seismic_build_index_gpu(const seismic_csr* docs, const seismic_bu
     if (!rc) rc = dalloc(F.p, a.sum_code, sum_cap);
     if (!rc) rc = dalloc(F.p, a.sum_bump, 1);
     if (!rc) rc = dalloc(F.p, a.flags, 1);
-    a.s_ncap = n_max;
+    a.s_ncap = P.n_max;
     a.s_ecap = ecap;
-    if (!rc) rc = dalloc(F.p, a.s_perm, (size_t)grid * n_max);
-    if (!rc) rc = dalloc(F.p, a.s_assign, (size_t)grid * n_max);
+    if (!rc) rc = dalloc(F.p, a.s_perm, (size_t)grid * P.n_max);
+    if (!rc) rc = dalloc(F.p, a.s_assign, (size_t)grid * P.n_max);
     if (!rc) rc = dalloc(F.p, a.s_tcount, (size_t)grid * dim);
     if (!rc) rc = dalloc(F.p, a.s_tstart, (size_t)grid * dim);
     if (!rc) rc = dalloc(F.p, a.s_tfill, (size_t)grid * dim);
@@ -659,36 +645,193 @@ extern "C" int seismic_build_index_gpu(const seismic_csr* docs, const seismic_bu
     while (sortcap < dim) sortcap <<= 1;
     a.s_sortcap = sortcap;
     if (!rc) rc = dalloc(F.p, a.s_sort, (size_t)grid * sortcap);
-    if (rc) { delete ix; return rc; }
+    if (rc) return rc;
     bool ok = hipMemset(d_q, 0, 4) == hipSuccess && hipMemset(a.sum_bump, 0, 8) == hipSuccess &&
               hipMemset(a.t_nblk, 0, (size_t)dim * 4) == hipSuccess &&
               hipMemset(a.flags, 0, 4) == hipSuccess &&
               hipMemset(a.s_tcount, 0, (size_t)grid * dim * 4) == hipSuccess &&
               hipMemset(a.s_tfill, 0, (size_t)grid * dim * 4) == hipSuccess &&
               hipMemset(a.s_phi, 0, (size_t)grid * dim * 4) == hipSuccess;
-    if (!ok) { delete ix; return fail(SEISMIC_EHIP, "gpu build: memset failed"); }
-    if (p->verbose) std::fprintf(stderr, "gpu build: inputs on the device (%.1f s)\n", elapsed());
-    uint32_t flags = 0;
+    if (!ok) return fail(SEISMIC_EHIP, "gpu build: memset failed");
+    flags = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        hipLaunchKernelGGL(k_build_terms, dim3(grid), dim3(kBT), 0, nullptr, a);
-        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-            delete ix;
+        hipLaunchKernelGGL(seismic_dev::k_build_terms, dim3(grid), dim3(seismic_dev::kBT), 0, nullptr, a);
+        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
             return fail(SEISMIC_EHIP, "gpu build: kernel failed");
-        }
         (void)hipMemcpy(&flags, a.flags, 4, hipMemcpyDeviceToHost);
         if (flags != 4u || attempt == 1) break;
         // only the summary region was short: run again with its exact size
         unsigned long long need = 0;
         (void)hipMemcpy(&need, a.sum_bump, 8, hipMemcpyDeviceToHost);
         if (p->verbose) std::fprintf(stderr, "gpu build: %llu summary entries, rerunning with room for them\n", need);
+        F.drop(a.sum_term);
+        F.drop(a.sum_code);
         a.sum_cap = need;
         rc = dalloc(F.p, a.sum_term, need);
         if (!rc) rc = dalloc(F.p, a.sum_code, need);
-        if (rc) { delete ix; return rc; }
+        if (rc) return rc;
         ok = hipMemset(d_q, 0, 4) == hipSuccess && hipMemset(a.sum_bump, 0, 8) == hipSuccess &&
              hipMemset(a.flags, 0, 4) == hipSuccess && hipMemset(a.t_nblk, 0, (size_t)dim * 4) == hipSuccess;
-        if (!ok) { delete ix; return fail(SEISMIC_EHIP, "gpu build: memset failed"); }
+        if (!ok) return fail(SEISMIC_EHIP, "gpu build: memset failed");
     }
+    // the per-workgroup scratch is no longer needed
+    for (void* x : {(void*)a.s_perm, (void*)a.s_assign, (void*)a.s_tcount, (void*)a.s_tstart, (void*)a.s_tfill,
+                    (void*)a.s_touched, (void*)a.s_phi, (void*)a.s_ck, (void*)a.s_cv, (void*)a.s_sort})
+        F.drop(x);
+    return SEISMIC_OK;
+}
+
+// The per-block outputs in canonical order (terms ascending, each term's
+// blocks in slot order) written into H's per-block arrays; src_at[j] =
+// where canonical block j's summary sits in the kernel's bump region.
+int canonical_blocks(const BuildArgs& a, const uint64_t* d_bsat, const Plan& P, uint32_t dim, HostIndex& H,
+                     std::vector<uint64_t>& src_at, uint64_t& used) {
+    const uint64_t total_b = P.total_b;
+    std::vector<uint32_t> nblk(dim), b_len(total_b), b_cent(total_b), b_sum_len(total_b);
+    std::vector<float> b_m(total_b), b_delta(total_b);
+    std::vector<uint64_t> b_sum_at(total_b);
+    used = 0;
+    bool ok = hipMemcpy(nblk.data(), a.t_nblk, dim * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(b_len.data(), a.b_len, total_b * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(b_cent.data(), a.b_cent, total_b * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(b_sum_len.data(), a.b_sum_len, total_b * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(b_m.data(), a.b_m, total_b * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(b_delta.data(), a.b_delta, total_b * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(b_sum_at.data(), d_bsat, total_b * 8, hipMemcpyDeviceToHost) == hipSuccess &&
+              hipMemcpy(&used, a.sum_bump, 8, hipMemcpyDeviceToHost) == hipSuccess;
+    if (!ok) return fail(SEISMIC_EHIP, "gpu build: download failed");
+    H.list_off.assign(dim + 1, 0);
+    for (uint32_t t = 0; t < dim; ++t) H.list_off[t + 1] = H.list_off[t] + nblk[t];
+    const uint64_t nbt = H.list_off[dim];
+    H.blk_post_off.assign(nbt + 1, 0);
+    H.blk_sum_off.assign(nbt + 1, 0);
+    H.blk_m.resize(nbt);
+    H.blk_delta.resize(nbt);
+    H.blk_centroid.resize(nbt);
+    src_at.resize(nbt);
+    for (uint32_t t = 0; t < dim; ++t)
+        for (uint32_t j = 0; j < nblk[t]; ++j) {
+            const uint64_t src = P.t_bcap[t] + j, dst = H.list_off[t] + j;
+            H.blk_post_off[dst + 1] = H.blk_post_off[dst] + b_len[src];
+            H.blk_sum_off[dst + 1] = H.blk_sum_off[dst] + b_sum_len[src];
+            H.blk_m[dst] = b_m[src];
+            H.blk_delta[dst] = b_delta[src];
+            H.blk_centroid[dst] = b_cent[src];
+            src_at[dst] = b_sum_at[src];
+        }
+    return SEISMIC_OK;
+}
+
+void set_params(HostIndex& H, const seismic_csr* docs, const seismic_build_params* p) {
+    H.dim = docs->dim;
+    H.n_docs = docs->n_rows;
+    H.lambda = p->lambda;
+    H.beta = p->beta;
+    H.gamma = p->gamma;
+    H.seed = p->seed;
+    H.alpha = p->alpha;
+}
+
+int check_build_params(const seismic_build_params* p) {
+    if (p->lambda < 1) return fail(SEISMIC_EINVAL, "build: lambda must be >= 1");
+    if (p->beta < 1) return fail(SEISMIC_EINVAL, "build: beta must be >= 1");
+    if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return fail(SEISMIC_EINVAL, "build: gamma must be in (0, 1]");
+    if (!(p->alpha >= 0.0 && p->alpha <= 1.0)) return fail(SEISMIC_EINVAL, "build: alpha must be in [0, 1]");
+    return SEISMIC_OK;
+}
+
+// A wave per canonical block copies its summary out of the bump region.
+__global__ __launch_bounds__(256) void k_gather_sums(const uint64_t* src_at, const uint64_t* dst_off, uint64_t nbt,
+                                                     const uint16_t* st, const uint8_t* sc, uint16_t* ot,
+                                                     uint8_t* oc) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / kWave);
+    for (uint64_t j = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; j < nbt; j += waves) {
+        const uint64_t at = src_at[j], to = dst_off[j], len = dst_off[j + 1] - to;
+        for (uint64_t e = lane; e < len; e += kWave) {
+            ot[to + e] = st[at + e];
+            oc[to + e] = sc[at + e];
+        }
+    }
+}
+
+template <typename T>
+int index_buffer(DeviceIndex* d, size_t n, size_t pad, const T*& out, T** mut = nullptr) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>((n + pad) * sizeof(T), 16);
+    if (hipMalloc(&p, bytes) != hipSuccess)
+        return fail(SEISMIC_ENOMEM, "device build: index allocation of %zu bytes failed", bytes);
+    d->allocs.push_back(p);
+    if (pad && hipMemset((uint8_t*)p + n * sizeof(T), 0, bytes - n * sizeof(T)) != hipSuccess)
+        return fail(SEISMIC_EHIP, "device build: memset failed");
+    out = (const T*)p;
+    if (mut) *mut = (T*)p;
+    return SEISMIC_OK;
+}
+
+template <typename T>
+int index_upload(DeviceIndex* d, const std::vector<T>& v, const T*& out) {
+    T* p = nullptr;
+    int rc = index_buffer(d, v.size(), 0, out, &p);
+    if (!rc && !v.empty() && hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        rc = fail(SEISMIC_EHIP, "device build: upload failed");
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int seismic_build_index_gpu(const seismic_csr* docs, const seismic_build_params* p, int device,
+                                       seismic_index** out) {
+    using namespace seismic_dev;
+    if (!out || !p || !docs) return fail(SEISMIC_EINVAL, "gpu build: null argument");
+    *out = nullptr;
+    int rc = check_build_params(p);
+    if (!rc) rc = validate_csr_host(docs, 65536, "build: docs");
+    if (rc) return rc;
+    if (docs->n_rows >= 0xFFFFFFFFull) return fail(SEISMIC_EINVAL, "build: more than 2^32-1 documents");
+    DeviceGuard g(device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "gpu build: cannot select device %d", device);
+    auto t_start = std::chrono::steady_clock::now();
+    auto elapsed = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
+    seismic_index* ix = new (std::nothrow) seismic_index();
+    if (!ix) return fail(SEISMIC_ENOMEM, "gpu build: host allocation failed");
+    HostIndex& H = ix->h;
+    const uint32_t dim = docs->dim;
+    const int nthreads = resolve_threads(p->n_threads);
+    try {
+        set_params(H, docs, p);
+        H.row_ptr.assign(docs->row_ptr, docs->row_ptr + docs->n_rows + 1);
+        H.words.assign(docs->words, docs->words + docs->nnz);
+    } catch (const std::bad_alloc&) {
+        delete ix;
+        return fail(SEISMIC_ENOMEM, "gpu build: host allocation failed");
+    }
+    uint32_t row_max = 1;
+    for (uint64_t d = 0; d < H.n_docs; ++d) row_max = std::max<uint32_t>(row_max, (uint32_t)(H.row_ptr[d + 1] - H.row_ptr[d]));
+    Frees F;
+    uint64_t* d_rp = nullptr;
+    uint32_t* d_w = nullptr;
+    rc = dupload(F.p, d_rp, H.row_ptr.data(), H.row_ptr.size());
+    if (!rc) rc = dupload(F.p, d_w, H.words.data(), H.words.size());
+    DevCsc csc;
+    std::vector<uint64_t> off;
+    if (!rc) rc = device_csc(d_rp, d_w, H.n_docs, dim, csc, &off);
+    if (rc) { delete ix; return rc; }
+    Plan P;
+    plan_terms(off, dim, p, P);
+    if (!plan_fits(P)) {
+        csc.release();
+        delete ix;
+        if (p->verbose) std::fprintf(stderr, "gpu build: lists beyond the GPU path's limits; building on the host\n");
+        return seismic_build_index(docs, p, out);
+    }
+    if (p->verbose) std::fprintf(stderr, "gpu build: column lists on the device (%.1f s)\n", elapsed());
+    BuildArgs a;
+    uint32_t flags = 0;
+    uint64_t* d_bsat = nullptr;
+    rc = run_terms(d_rp, d_w, dim, row_max, csc, P, p, device, F, a, flags, d_bsat);
+    csc.release();
+    if (rc) { delete ix; return rc; }
     if (flags) {
         delete ix;
         if (p->verbose) std::fprintf(stderr, "gpu build: a list exceeded the GPU path's capacities (%u); building on the host\n", flags);
@@ -697,60 +840,147 @@ extern "C" int seismic_build_index_gpu(const seismic_csr* docs, const seismic_bu
     if (p->verbose) std::fprintf(stderr, "gpu build: lists, blocks and summaries on the device (%.1f s)\n", elapsed());
     // assemble the host index in canonical order
     try {
-        std::vector<uint32_t> nblk(dim), b_len(total_b), b_cent(total_b), b_sum_len(total_b);
-        std::vector<float> b_m(total_b), b_delta(total_b);
-        std::vector<uint64_t> b_sum_at(total_b);
+        std::vector<uint64_t> src_at;
         uint64_t used = 0;
-        ok = hipMemcpy(nblk.data(), a.t_nblk, dim * 4, hipMemcpyDeviceToHost) == hipSuccess &&
-             hipMemcpy(b_len.data(), a.b_len, total_b * 4, hipMemcpyDeviceToHost) == hipSuccess &&
-             hipMemcpy(b_cent.data(), a.b_cent, total_b * 4, hipMemcpyDeviceToHost) == hipSuccess &&
-             hipMemcpy(b_sum_len.data(), a.b_sum_len, total_b * 4, hipMemcpyDeviceToHost) == hipSuccess &&
-             hipMemcpy(b_m.data(), a.b_m, total_b * 4, hipMemcpyDeviceToHost) == hipSuccess &&
-             hipMemcpy(b_delta.data(), a.b_delta, total_b * 4, hipMemcpyDeviceToHost) == hipSuccess &&
-             hipMemcpy(b_sum_at.data(), d_bsat, total_b * 8, hipMemcpyDeviceToHost) == hipSuccess &&
-             hipMemcpy(&used, a.sum_bump, 8, hipMemcpyDeviceToHost) == hipSuccess;
-        H.postings.resize(total_n);
-        if (ok && total_n)
-            ok = hipMemcpy(H.postings.data(), a.postings, total_n * 4, hipMemcpyDeviceToHost) == hipSuccess;
+        rc = canonical_blocks(a, d_bsat, P, dim, H, src_at, used);
+        if (rc) { delete ix; return rc; }
+        H.postings.resize(P.total_n);
+        bool ok = true;
+        if (P.total_n) ok = hipMemcpy(H.postings.data(), a.postings, P.total_n * 4, hipMemcpyDeviceToHost) == hipSuccess;
         std::vector<uint16_t> st(used);
         std::vector<uint8_t> sc(used);
         if (ok && used)
             ok = hipMemcpy(st.data(), a.sum_term, used * 2, hipMemcpyDeviceToHost) == hipSuccess &&
                  hipMemcpy(sc.data(), a.sum_code, used, hipMemcpyDeviceToHost) == hipSuccess;
         if (!ok) { delete ix; return fail(SEISMIC_EHIP, "gpu build: download failed"); }
-        H.list_off.assign(dim + 1, 0);
-        for (uint32_t t = 0; t < dim; ++t) H.list_off[t + 1] = H.list_off[t] + nblk[t];
         const uint64_t nbt = H.list_off[dim];
-        H.blk_post_off.assign(nbt + 1, 0);
-        H.blk_sum_off.assign(nbt + 1, 0);
-        H.blk_m.resize(nbt);
-        H.blk_delta.resize(nbt);
-        H.blk_centroid.resize(nbt);
-        for (uint32_t t = 0; t < dim; ++t)
-            for (uint32_t j = 0; j < nblk[t]; ++j) {
-                const uint64_t src = t_bcap[t] + j, dst = H.list_off[t] + j;
-                H.blk_post_off[dst + 1] = H.blk_post_off[dst] + b_len[src];
-                H.blk_sum_off[dst + 1] = H.blk_sum_off[dst] + b_sum_len[src];
-                H.blk_m[dst] = b_m[src];
-                H.blk_delta[dst] = b_delta[src];
-                H.blk_centroid[dst] = b_cent[src];
-            }
         H.sum_term.resize(H.blk_sum_off[nbt]);
         H.sum_code.resize(H.blk_sum_off[nbt]);
-        parallel_for(dim, nthreads, 64, [&](int64_t ti, int) {
-            const uint32_t t = (uint32_t)ti;
-            for (uint32_t j = 0; j < nblk[t]; ++j) {
-                const uint64_t src = t_bcap[t] + j, dst = H.list_off[t] + j;
-                const uint64_t len = b_sum_len[src], at = b_sum_at[src], to = H.blk_sum_off[dst];
-                std::memcpy(H.sum_term.data() + to, st.data() + at, len * 2);
-                std::memcpy(H.sum_code.data() + to, sc.data() + at, len);
-            }
+        parallel_for((int64_t)nbt, nthreads, 4096, [&](int64_t j, int) {
+            const uint64_t len = H.blk_sum_off[j + 1] - H.blk_sum_off[j], at = src_at[j], to = H.blk_sum_off[j];
+            std::memcpy(H.sum_term.data() + to, st.data() + at, len * 2);
+            std::memcpy(H.sum_code.data() + to, sc.data() + at, len);
         });
     } catch (const std::bad_alloc&) {
         delete ix;
         return fail(SEISMIC_ENOMEM, "gpu build: host allocation failed");
     }
     if (p->verbose) std::fprintf(stderr, "gpu build: done (%.1f s)\n", elapsed());
+    *out = ix;
+    return SEISMIC_OK;
+}
+
+extern "C" int seismic_build_index_device(const seismic_csr* docs, const seismic_build_params* p, int device,
+                                          seismic_index** out) {
+    using namespace seismic_dev;
+    if (!out || !p || !docs) return fail(SEISMIC_EINVAL, "device build: null argument");
+    *out = nullptr;
+    int rc = check_build_params(p);
+    if (rc) return rc;
+    if (docs->n_rows >= 0xFFFFFFFFull) return fail(SEISMIC_EINVAL, "build: more than 2^32-1 documents");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(SEISMIC_EINVAL, "device build: device %d of %d", device, ndev);
+    DeviceGuard g(device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "device build: cannot select device %d", device);
+    auto t_start = std::chrono::steady_clock::now();
+    auto elapsed = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
+    uint32_t row_max = 0;
+    rc = validate_csr_device(docs, 65536, "device build: docs", &row_max);
+    if (rc) return rc;
+    const uint32_t dim = docs->dim;
+    const uint64_t n_docs = docs->n_rows, nnz = docs->nnz;
+    DevCsc csc;
+    std::vector<uint64_t> off;
+    rc = device_csc(docs->row_ptr, docs->words, n_docs, dim, csc, &off);
+    if (rc) return rc;
+    Plan P;
+    plan_terms(off, dim, p, P);
+    if (!plan_fits(P)) {
+        csc.release();
+        return fail(SEISMIC_EINVAL, "device build: a list needs %u blocks or %u postings (at most %u and %u)", P.nb_max,
+                    P.n_max, kMaxNb, 1u << 24);
+    }
+    if (p->verbose) std::fprintf(stderr, "device build: column lists (%.1f s)\n", elapsed());
+    Frees F;
+    BuildArgs a;
+    uint32_t flags = 0;
+    uint64_t* d_bsat = nullptr;
+    rc = run_terms(docs->row_ptr, docs->words, dim, row_max, csc, P, p, device, F, a, flags, d_bsat);
+    csc.release();
+    if (rc) return rc;
+    if (flags) return fail(SEISMIC_EINVAL, "device build: a list exceeded the kernel's capacities (%u)", flags);
+    F.drop(a.list_docs);
+    if (p->verbose) std::fprintf(stderr, "device build: lists, blocks and summaries (%.1f s)\n", elapsed());
+    seismic_index* ix = new (std::nothrow) seismic_index();
+    if (!ix) return fail(SEISMIC_ENOMEM, "device build: host allocation failed");
+    HostIndex& H = ix->h;
+    std::vector<uint64_t> src_at;
+    uint64_t used = 0;
+    try {
+        set_params(H, docs, p);
+        rc = canonical_blocks(a, d_bsat, P, dim, H, src_at, used);
+    } catch (const std::bad_alloc&) {
+        rc = fail(SEISMIC_ENOMEM, "device build: host allocation failed");
+    }
+    if (rc) { delete ix; return rc; }
+    const uint64_t nbt = H.list_off[dim], n_sums = H.blk_sum_off[nbt];
+    uint32_t mb = H.max_blocks_per_list(), cap = 2;
+    while (cap < mb) cap <<= 1;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ix; return fail(SEISMIC_EHIP, "device build: device query failed"); }
+    DeviceIndex* d = new DeviceIndex();
+    d->device = device;
+    d->sort_cap = cap;
+    d->smem_limit = prop.sharedMemPerBlock;
+    ix->dev = d;
+    ix->device_only = true;
+    ix->dev_nnz = nnz;
+    ix->dev_postings = P.total_n;
+    ix->dev_sums = n_sums;
+    seismic_dev::DevIdx& v = d->view;
+    auto bail = [&](int code) {
+        seismic_index_free(ix);
+        return code;
+    };
+    // per-block arrays, then the summaries gathered into canonical order
+    rc = index_upload(d, H.list_off, v.list_off);
+    if (!rc) rc = index_upload(d, H.blk_post_off, v.blk_post_off);
+    if (!rc) rc = index_upload(d, H.blk_sum_off, v.blk_sum_off);
+    if (!rc) rc = index_upload(d, H.blk_m, v.blk_m);
+    if (!rc) rc = index_upload(d, H.blk_delta, v.blk_delta);
+    uint16_t* st = nullptr;
+    uint8_t* sc = nullptr;
+    if (!rc) rc = index_buffer(d, n_sums, 16, v.sum_term, &st);
+    if (!rc) rc = index_buffer(d, n_sums, 16, v.sum_code, &sc);
+    uint64_t* d_src = nullptr;
+    if (!rc) rc = dupload(F.p, d_src, src_at.data(), src_at.size());
+    if (rc) return bail(rc);
+    if (nbt) {
+        const uint64_t grid = std::min<uint64_t>(16384, (nbt + 3) / 4);
+        hipLaunchKernelGGL(k_gather_sums, dim3((uint32_t)grid), dim3(256), 0, nullptr, d_src, v.blk_sum_off, nbt,
+                           a.sum_term, a.sum_code, st, sc);
+        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+            return bail(fail(SEISMIC_EHIP, "device build: summary gather failed"));
+    }
+    F.drop(a.sum_term);
+    F.drop(a.sum_code);
+    // the postings are already in canonical order
+    F.take(a.postings);
+    d->allocs.push_back(a.postings);
+    v.postings = a.postings;
+    // the forward index: a copy of the caller's rows (zero words after the end for vector loads)
+    uint64_t* rp = nullptr;
+    uint32_t* w = nullptr;
+    rc = index_buffer(d, n_docs + 1, 0, v.row_ptr, &rp);
+    if (!rc) rc = index_buffer(d, nnz, 8, v.words, &w);
+    if (rc) return bail(rc);
+    if (hipMemcpy(rp, docs->row_ptr, (n_docs + 1) * 8, hipMemcpyDeviceToDevice) != hipSuccess ||
+        (nnz && hipMemcpy(w, docs->words, nnz * 4, hipMemcpyDeviceToDevice) != hipSuccess))
+        return bail(fail(SEISMIC_EHIP, "device build: forward index copy failed"));
+    v.dim = dim;
+    v.n_docs = (uint32_t)n_docs;
+    if (p->verbose) std::fprintf(stderr, "device build: done (%.1f s)\n", elapsed());
     *out = ix;
     return SEISMIC_OK;
 }

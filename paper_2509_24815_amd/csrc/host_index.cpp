@@ -646,23 +646,43 @@ int seismic_build_index(const seismic_csr* docs, const seismic_build_params* par
 
 int seismic_index_serialized_size(const seismic_index* index, uint64_t* bytes) {
     if (!index || !bytes) return fail(SEISMIC_EINVAL, "serialized_size: null argument");
-    *bytes = serialized_size(index->h);
+    const HostIndex& h = index->h;
+    SectionView sv[11];
+    sections_of(h, sv);
+    if (index->device_only) {  // the device-resident sections, by size
+        sv[0].bytes = 8 * (h.n_docs + 1);
+        sv[1].bytes = 4 * index->dev_nnz;
+        sv[8].bytes = 4 * index->dev_postings;
+        sv[9].bytes = 2 * index->dev_sums;
+        sv[10].bytes = index->dev_sums;
+    }
+    uint64_t off = kHeaderBytes;
+    for (auto& v : sv) off = al64(off) + v.bytes;
+    *bytes = al64(off);
     return SEISMIC_OK;
 }
 
 int seismic_index_serialize(const seismic_index* index, void* buf, uint64_t bytes) {
     if (!index || !buf) return fail(SEISMIC_EINVAL, "serialize: null argument");
-    if (bytes < serialized_size(index->h)) return fail(SEISMIC_EINVAL, "serialize: buffer too small");
-    serialize(index->h, (uint8_t*)buf);
+    HostIndex tmp;
+    const HostIndex* h = nullptr;
+    int rc = full_host_index(index, tmp, &h);
+    if (rc) return rc;
+    if (bytes < serialized_size(*h)) return fail(SEISMIC_EINVAL, "serialize: buffer too small");
+    serialize(*h, (uint8_t*)buf);
     return SEISMIC_OK;
 }
 
 int seismic_index_save(const seismic_index* index, const char* path) {
     if (!index || !path) return fail(SEISMIC_EINVAL, "save: null argument");
-    uint64_t n = serialized_size(index->h);
+    HostIndex tmp;
+    const HostIndex* h = nullptr;
+    int rc = full_host_index(index, tmp, &h);
+    if (rc) return rc;
+    uint64_t n = serialized_size(*h);
     std::vector<uint8_t> buf;
     try { buf.resize(n); } catch (const std::bad_alloc&) { return fail(SEISMIC_ENOMEM, "save: host allocation failed"); }
-    serialize(index->h, buf.data());
+    serialize(*h, buf.data());
     FILE* f = std::fopen(path, "wb");
     if (!f) return fail(SEISMIC_EIO, "save: cannot open %s", path);
     size_t w = std::fwrite(buf.data(), 1, n, f);
@@ -696,8 +716,10 @@ int seismic_index_load(const char* path, seismic_index** out) {
 int seismic_index_info(const seismic_index* index, uint64_t out[10]) {
     if (!index || !out) return fail(SEISMIC_EINVAL, "info: null argument");
     const HostIndex& h = index->h;
-    out[0] = h.dim; out[1] = h.n_docs; out[2] = h.nnz(); out[3] = h.n_blocks();
-    out[4] = h.postings.size(); out[5] = h.sum_term.size(); out[6] = h.lambda; out[7] = h.beta;
+    out[0] = h.dim; out[1] = h.n_docs; out[2] = index->nnz(); out[3] = h.n_blocks();
+    out[4] = index->device_only ? index->dev_postings : h.postings.size();
+    out[5] = index->device_only ? index->dev_sums : h.sum_term.size();
+    out[6] = h.lambda; out[7] = h.beta;
     out[8] = h.max_blocks_per_list();
     out[9] = device_index_layout(index->dev);
     return SEISMIC_OK;

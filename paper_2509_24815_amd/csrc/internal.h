@@ -135,4 +135,18 @@ struct seismic_index {
     seismic::HostIndex h;
     DeviceIndex* dev = nullptr;
     std::mutex mu;  // guards lazy device-side structures (exact search)
+    // Built on a device and kept there (seismic_build_index_device): h holds
+    // the parameters and the per-block arrays, but no forward index, postings
+    // or summaries; their sizes are below.
+    bool device_only = false;
+    uint64_t dev_nnz = 0, dev_postings = 0, dev_sums = 0;
+    uint64_t nnz() const { return device_only ? dev_nnz : h.nnz(); }
 };
+
+namespace seismic {
+// The complete host form of a device-only index: h's arrays plus the forward
+// index, postings and summaries copied back from the device (synchronous).
+int download_host_index(const seismic_index* index, HostIndex& out);
+// The host form to serialize: index->h itself, or a download into tmp.
+int full_host_index(const seismic_index* index, HostIndex& tmp, const HostIndex** out);
+}  // namespace seismic
