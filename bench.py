@@ -35,6 +35,12 @@ WORKLOADS = {
                cut=10, hfs=HF_SWEEP),
     "100k": dict(n_docs=100_000, n_queries=1000, qlaw="poisson", lam=1000, beta=50, gamma=0.4,
                  cut=10, hfs=HF_SWEEP),
+    # the scale study's collection shape (138M passages, 127 / 44 nonzeros per
+    # document / query, lambda 6e4), generated straight into HBM and indexed
+    # there: it does not fit the host's memory alongside its index
+    "msmarco-v2-138M": dict(n_docs=138_000_000, n_queries=3903, qlaw="poisson", qmean=44.0, dmean=127.0,
+                            lam=60000, beta=400, gamma=0.4, cut=10, hfs=(0.1, 0.15, 0.2) + HF_SWEEP,
+                            device_build=True),
 }
 
 PEAK_HBM_GBS = 8000.0
@@ -92,6 +98,41 @@ def alg_bytes(counters: np.ndarray, q_nnz: np.ndarray, k: int) -> np.ndarray:
             + 4 * c[:, 4] + 8 * k)
 
 
+def device_collection(torch, synth, n_docs, mean, chunk=2_000_000):
+    """The document stream's rows 0 .. n_docs - 1 generated on the host in
+    chunks (the next chunk drawn while the last one is copied) into device
+    tensors: row_ptr int64 [n_docs + 1], words int32 [nnz]."""
+    from concurrent.futures import ThreadPoolExecutor
+    dev = torch.device("cuda", 0)
+    counts = synth.row_counts(n_docs, seed=0, mean=mean, lo=10, hi=400)
+    rp = np.zeros(n_docs + 1, dtype=np.int64)
+    np.cumsum(counts, out=rp[1:])
+    del counts
+    nnz = int(rp[-1])
+    log(f"[bench] {n_docs} documents, {nnz} nonzeros ({nnz * 4 / 1e9:.1f} GB of words)")
+    rp_dev = torch.from_numpy(rp).to(dev)
+    w_dev = torch.empty(nnz, dtype=torch.int32, device=dev)
+    starts = list(range(0, n_docs, chunk))
+
+    def gen(r0):
+        return synth.generate(min(chunk, n_docs - r0), seed=0, mean=mean, lo=10, hi=400, row0=r0)
+
+    t0 = time.time()
+    with ThreadPoolExecutor(1) as ex:
+        fut = ex.submit(gen, starts[0])
+        for i, r0 in enumerate(starts):
+            part = fut.result()
+            if i + 1 < len(starts):
+                fut = ex.submit(gen, starts[i + 1])
+            a = int(rp[r0])
+            assert part.nnz == int(rp[r0 + part.n_rows]) - a
+            w_dev[a:a + part.nnz].copy_(torch.from_numpy(part.words.view(np.int32)))
+            if i % 10 == 9 or i + 1 == len(starts):
+                log(f"[bench] generated {r0 + part.n_rows} documents ({time.time() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return rp_dev, w_dev, nnz
+
+
 def serve_run(binding, ix, qs, rate, seconds, k, cut, hf, probe, tau, max_batch=1024, slots=4):
     """Open-loop Poisson arrivals at `rate` queries/s for `seconds` (queries
     cycle through the batch), served by the library's serving loop.
@@ -146,6 +187,7 @@ def main():
     ap.add_argument("--knn-cut", type=int, default=10, help="query_cut of the graph-building searches")
     ap.add_argument("--knn-hf", type=float, default=0.5, help="heap_factor of the graph-building searches")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per serving rate")
+    ap.add_argument("--n-docs", type=int, default=0, help="override the workload's document count")
     ap.add_argument("--probe", default=os.path.join(ROOT, "paper_2509_24815_amd", "probes", "probe_1m.npy"),
                     help="learned block-probe weights to evaluate beside the heap_factor rule ('' = skip)")
     args = ap.parse_args()
@@ -170,41 +212,66 @@ def main():
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
 
+    n_docs = args.n_docs or W["n_docs"]
+    on_device = W.get("device_build", False)
     t0 = time.time()
-    log(f"[bench] workload {args.workload}: generating {W['n_docs']} docs (host cores: {os.cpu_count()})")
-    docs = synth.docs(W["n_docs"], seed=0)
-    qs = synth.queries(W["n_queries"], seed=0, law=W["qlaw"])
-    log(f"[bench] generated {docs.nnz} doc nonzeros, {qs.nnz} query nonzeros ({time.time() - t0:.1f} s)")
-    t1 = time.time()
-    cache = args.index_cache
-    if cache and os.path.exists(cache):
-        ix = Index.load(cache)
-        build_s = None
-        log(f"[bench] index loaded from {cache} in {time.time() - t1:.1f} s")
-    else:
-        builder = Index.build if args.host_build else Index.build_gpu
-        ix = builder(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, verbose=True,
-                     alpha=args.alpha)
+    hbm = None
+    if on_device:
+        # collection and index live only in HBM: no host oracle, graph, probe or serving legs
+        args.cpu_seconds, args.knn, args.probe, args.no_serve = 0.0, 0, "", True
+        log(f"[bench] workload {args.workload}: generating {n_docs} docs into HBM (host cores: {os.cpu_count()})")
+        rp_dev, w_dev, doc_nnz = device_collection(torch, synth, n_docs, W["dmean"])
+        qs = synth.generate(W["n_queries"], seed=0, stream=synth.STREAM_QUERIES, law=W["qlaw"], mean=W["qmean"],
+                            lo=1, hi=400)
+        log(f"[bench] generated {doc_nnz} doc nonzeros, {qs.nnz} query nonzeros ({time.time() - t0:.1f} s)")
+        docs = None
+        t1 = time.time()
+        ix = Index.build_device(binding.device_csr(rp_dev, w_dev, synth.DIM), W["lam"], W["beta"], W["gamma"],
+                                seed=0, verbose=True, alpha=args.alpha)
         build_s = time.time() - t1
-        log(f"[bench] index built in {build_s:.1f} s")
-        if cache:
-            ix.save(cache)
-            log(f"[bench] index saved to {cache}")
-    info = ix.info()
-    log(f"[bench] index: {info}")
-    t1 = time.time()
-    layout = "block_rows"
-    try:
-        ix.upload(0, block_rows=not args.plain_rows)
-        layout = "rows" if args.plain_rows else "block_rows"
-    except Exception as e:  # not enough HBM for the block-major copies
-        log(f"[bench] block-major rows unavailable ({e}); plain rows")
-        ix.close()
-        ix = Index.load(cache) if cache and os.path.exists(cache) else \
-            Index.build(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, alpha=args.alpha)
-        ix.upload(0)
+        log(f"[bench] index built on the device in {build_s:.1f} s")
+        del rp_dev, w_dev
+        torch.cuda.empty_cache()
+        free, total = torch.cuda.mem_get_info()
+        hbm = {"index_resident_gb": round((total - free) / 1e9, 1), "device_total_gb": round(total / 1e9, 1)}
+        info = ix.info()
+        log(f"[bench] index: {info}; HBM in use {hbm}")
         layout = "rows"
-    log(f"[bench] index resident in HBM ({layout}, {time.time() - t1:.1f} s)")
+    else:
+        log(f"[bench] workload {args.workload}: generating {n_docs} docs (host cores: {os.cpu_count()})")
+        docs = synth.docs(n_docs, seed=0)
+        qs = synth.queries(W["n_queries"], seed=0, law=W["qlaw"])
+        log(f"[bench] generated {docs.nnz} doc nonzeros, {qs.nnz} query nonzeros ({time.time() - t0:.1f} s)")
+        t1 = time.time()
+        cache = args.index_cache
+        if cache and os.path.exists(cache):
+            ix = Index.load(cache)
+            build_s = None
+            log(f"[bench] index loaded from {cache} in {time.time() - t1:.1f} s")
+        else:
+            builder = Index.build if args.host_build else Index.build_gpu
+            ix = builder(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, verbose=True,
+                         alpha=args.alpha)
+            build_s = time.time() - t1
+            log(f"[bench] index built in {build_s:.1f} s")
+            if cache:
+                ix.save(cache)
+                log(f"[bench] index saved to {cache}")
+        info = ix.info()
+        log(f"[bench] index: {info}")
+        t1 = time.time()
+        layout = "block_rows"
+        try:
+            ix.upload(0, block_rows=not args.plain_rows)
+            layout = "rows" if args.plain_rows else "block_rows"
+        except Exception as e:  # not enough HBM for the block-major copies
+            log(f"[bench] block-major rows unavailable ({e}); plain rows")
+            ix.close()
+            ix = Index.load(cache) if cache and os.path.exists(cache) else \
+                Index.build(docs, W["lam"], W["beta"], W["gamma"], seed=0, n_threads=args.threads, alpha=args.alpha)
+            ix.upload(0)
+            layout = "rows"
+        log(f"[bench] index resident in HBM ({layout}, {time.time() - t1:.1f} s)")
 
     q_rp = torch.from_numpy(qs.row_ptr.astype(np.int64)).to(dev)
     q_w = torch.from_numpy(qs.words.view(np.int32)).to(dev)
@@ -510,14 +577,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f16xf16->f64 accumulate, f32 out",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {W['n_docs']} docs, {nq}-query batch ({W['qlaw']} nnz), "
+        "config": {"workload": f"{args.workload}: {n_docs} docs, {nq}-query batch ({W['qlaw']} nnz), "
                                f"lambda {W['lam']}, beta {W['beta']}, gamma {W['gamma']}, "
                                + (f"alpha {args.alpha}, " if args.alpha else "")
                                + (f"query_mass {qmass}, " if qmass else f"query_cut {cut}, ")
                                + f"k {k}, heap_factor {chosen}",
                    f"recall_at_{k}": point["recall"], "recall_target": args.recall,
                    "index_build_s": None if build_s is None else round(build_s, 1),
-                   "index_build": "cached" if build_s is None else ("host" if args.host_build else "gpu"),
+                   "index_build": "cached" if build_s is None else
+                   ("device-resident" if on_device else "host" if args.host_build else "gpu"),
+                   "hbm": hbm,
                    "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
                    "sweep": sweep, "learned_probe": learned, "knn_refined": refined, "grid": grid},
         "serving": serving,

@@ -601,7 +601,6 @@ int run_terms(const uint64_t* d_rp, const uint32_t* d_w, uint32_t dim, uint32_t 
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(SEISMIC_EHIP, "gpu build: device query failed");
     const uint32_t grid = (uint32_t)std::max(1, prop.multiProcessorCount) * 2;
     const uint64_t ecap = (uint64_t)P.nb_max * std::max<uint32_t>(row_max, 1);
-    const uint64_t sum_cap = std::min<uint64_t>(std::max<uint64_t>(P.total_b * 256, 1 << 20), 4000000000ull);
     uint32_t *d_order = nullptr, *d_tn = nullptr, *d_tnb = nullptr, *d_q = nullptr;
     uint64_t *d_tpost = nullptr, *d_tbcap = nullptr;
     a = BuildArgs{};
@@ -614,7 +613,7 @@ int run_terms(const uint64_t* d_rp, const uint32_t* d_w, uint32_t dim, uint32_t 
     if (!rc) rc = dalloc(F.p, d_q, 4);
     a.row_ptr = d_rp; a.words = d_w; a.dim = dim; a.csc_off = csc.off; a.csc_doc = csc.doc; a.csc_val = csc.val;
     a.order = d_order; a.n_work = (uint32_t)P.order.size(); a.t_n = d_tn; a.t_nb = d_tnb; a.t_post = d_tpost;
-    a.t_bcap = d_tbcap; a.queue = d_q; a.seed = p->seed; a.gamma = p->gamma; a.sum_cap = sum_cap;
+    a.t_bcap = d_tbcap; a.queue = d_q; a.seed = p->seed; a.gamma = p->gamma;
     const uint64_t total_n = P.total_n, total_b = P.total_b;
     if (!rc) rc = dalloc(F.p, a.list_docs, total_n);
     if (!rc) rc = dalloc(F.p, a.postings, total_n);
@@ -626,8 +625,6 @@ int run_terms(const uint64_t* d_rp, const uint32_t* d_w, uint32_t dim, uint32_t 
     if (!rc) rc = dalloc(F.p, d_bsat, total_b);
     a.b_sum_at = d_bsat;
     if (!rc) rc = dalloc(F.p, a.b_sum_len, total_b);
-    if (!rc) rc = dalloc(F.p, a.sum_term, sum_cap);
-    if (!rc) rc = dalloc(F.p, a.sum_code, sum_cap);
     if (!rc) rc = dalloc(F.p, a.sum_bump, 1);
     if (!rc) rc = dalloc(F.p, a.flags, 1);
     a.s_ncap = P.n_max;
@@ -646,6 +643,19 @@ int run_terms(const uint64_t* d_rp, const uint32_t* d_w, uint32_t dim, uint32_t 
     a.s_sortcap = sortcap;
     if (!rc) rc = dalloc(F.p, a.s_sort, (size_t)grid * sortcap);
     if (rc) return rc;
+    // the summary region, sized last: room for 1024 entries per block where
+    // the free memory allows (at least 256; the kernel reports the exact
+    // need when the region is short, and the slices then run again)
+    {
+        size_t free_b = 0, total_mem = 0;
+        (void)hipMemGetInfo(&free_b, &total_mem);
+        const uint64_t lo = std::max<uint64_t>(P.total_b * 256, 1 << 20);
+        const uint64_t room = free_b > (4ull << 30) ? (free_b - (4ull << 30)) / 3 : 0;
+        a.sum_cap = std::max(lo, std::min<uint64_t>(P.total_b * 1024, room));
+    }
+    if (!rc) rc = dalloc(F.p, a.sum_term, a.sum_cap);
+    if (!rc) rc = dalloc(F.p, a.sum_code, a.sum_cap);
+    if (rc) return rc;
     bool ok = hipMemset(d_q, 0, 4) == hipSuccess && hipMemset(a.sum_bump, 0, 8) == hipSuccess &&
               hipMemset(a.t_nblk, 0, (size_t)dim * 4) == hipSuccess &&
               hipMemset(a.flags, 0, 4) == hipSuccess &&
@@ -653,11 +663,39 @@ int run_terms(const uint64_t* d_rp, const uint32_t* d_w, uint32_t dim, uint32_t 
               hipMemset(a.s_tfill, 0, (size_t)grid * dim * 4) == hipSuccess &&
               hipMemset(a.s_phi, 0, (size_t)grid * dim * 4) == hipSuccess;
     if (!ok) return fail(SEISMIC_EHIP, "gpu build: memset failed");
+    // launches over slices of the work order of about equal cost (kept
+    // postings times blocks, the assignment's size), so that a long build
+    // reports progress between launches
+    std::vector<uint32_t> cuts{0};
+    {
+        long double total = 0, run = 0;
+        for (uint32_t t : P.order) total += (long double)P.t_n[t] * P.t_nb[t] + P.t_n[t];
+        // about 2.5e10 units run in ten seconds; builds shorter than ~40 s stay one launch
+        const int n_slices = total > 1e11L ? (int)std::min<long double>(64, total / 2.5e10L + 1) : 1;
+        for (uint32_t w = 0; w < P.order.size(); ++w) {
+            const uint32_t t = P.order[w];
+            run += (long double)P.t_n[t] * P.t_nb[t] + P.t_n[t];
+            if (run * n_slices >= total * (long double)cuts.size() && cuts.size() < (size_t)n_slices) cuts.push_back(w + 1);
+        }
+        if (cuts.back() != P.order.size()) cuts.push_back((uint32_t)P.order.size());
+    }
+    auto t0 = std::chrono::steady_clock::now();
     flags = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        hipLaunchKernelGGL(seismic_dev::k_build_terms, dim3(grid), dim3(seismic_dev::kBT), 0, nullptr, a);
-        if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
-            return fail(SEISMIC_EHIP, "gpu build: kernel failed");
+        const uint32_t* order0 = a.order;
+        for (size_t sl = 0; sl + 1 < cuts.size(); ++sl) {
+            BuildArgs as = a;
+            as.order = order0 + cuts[sl];
+            as.n_work = cuts[sl + 1] - cuts[sl];
+            if (hipMemset(d_q, 0, 4) != hipSuccess) return fail(SEISMIC_EHIP, "gpu build: memset failed");
+            hipLaunchKernelGGL(seismic_dev::k_build_terms, dim3(grid), dim3(seismic_dev::kBT), 0, nullptr, as);
+            if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+                return fail(SEISMIC_EHIP, "gpu build: kernel failed");
+            if (p->verbose && cuts.size() > 2)
+                std::fprintf(stderr, "gpu build: lists %u..%u of %zu done (%.1f s)\n", cuts[sl], cuts[sl + 1],
+                             P.order.size(),
+                             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        }
         (void)hipMemcpy(&flags, a.flags, 4, hipMemcpyDeviceToHost);
         if (flags != 4u || attempt == 1) break;
         // only the summary region was short: run again with its exact size

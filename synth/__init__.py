@@ -129,6 +129,20 @@ def generate(n_rows: int, *, seed: int = 0, stream: int = STREAM_DOCS, law: str 
     return CSR(row_ptr, words, dim)
 
 
+def row_counts(n_rows: int, *, seed: int = 0, stream: int = STREAM_DOCS, law: str = "poisson",
+               mean: float = 120.0, lo: int = 10, hi: int = 400, dim: int = DIM, zipf_s: float = ZIPF_S,
+               row0: int = 0) -> np.ndarray:
+    """Nonzero counts of rows row0 .. row0 + n_rows - 1 (the first draw of
+    each row, as generate() makes it), without drawing the rows."""
+    lib = _load()
+    counts = np.empty(n_rows, dtype=np.uint32)
+    rc = lib.synth_counts_range(row0, n_rows, dim, zipf_s, {"poisson": 0, "uniform": 1}[law], mean, lo, hi, seed,
+                                stream, counts.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise ValueError(f"synth_counts failed ({rc})")
+    return counts
+
+
 def docs(n_docs: int, seed: int = 0) -> CSR:
     """Documents: nnz ~ Poisson(120) clipped to [10, 400]."""
     return generate(n_docs, seed=seed, stream=STREAM_DOCS, law="poisson", mean=120.0, lo=10, hi=400)

@@ -40,6 +40,12 @@ def test_row_slices_concatenate():
         assert np.array_equal(part.row_ptr, whole.row_ptr[a:b + 1] - whole.row_ptr[a])
 
 
+def test_row_counts_match_rows():
+    whole = synth.generate(2000, seed=4, mean=127.0)
+    c = synth.row_counts(1500, seed=4, mean=127.0, row0=500)
+    assert np.array_equal(c.astype(np.uint64), np.diff(whole.row_ptr)[500:])
+
+
 def test_row_law_shape():
     d = synth.docs(4000, seed=1)
     lens = np.diff(d.row_ptr.astype(np.int64))
