@@ -98,6 +98,60 @@ def alg_bytes(counters: np.ndarray, q_nnz: np.ndarray, k: int) -> np.ndarray:
             + 4 * c[:, 4] + 8 * k)
 
 
+def unique_bytes(S: dict, qs, list_term: np.ndarray, prefix: np.ndarray, k: int) -> float:
+    """Compulsory bytes of one batch (layout of the library): what the batch
+    must read at least once, however many of its queries share it -- the
+    queries and results, every summary entry and block header of each
+    distinct visited list, and each distinct evaluated block's posting
+    offsets, postings, row offsets and rows.  The evaluated blocks are
+    recovered from the trace: the i-th visited list of query q evaluated the
+    first prefix[q, i] blocks in the order of Algorithm 2 (summary score
+    desc, block asc); the scores are recomputed from the index exactly (fp64
+    sums of fp16 x grid values, rounded to fp32)."""
+    import scipy.sparse as sp
+    nq = qs.n_rows
+    q_nnz = np.diff(qs.row_ptr.astype(np.int64))
+    total = float((8 + 4 * q_nnz).sum() + 8 * k * nq)
+    lo = S["list_off"].astype(np.int64)
+    so = S["blk_sum_off"].astype(np.int64)
+    po = S["blk_post_off"].astype(np.int64)
+    terms = list_term.astype(np.int64)
+    valid = list_term != 0xFFFFFFFF
+    ut = np.unique(terms[valid])
+    total += float((8 + 16 * (lo[ut + 1] - lo[ut]) + 3 * (so[lo[ut + 1]] - so[lo[ut]])).sum())
+    Q = sp.csr_matrix((qs.values().astype(np.float64), qs.terms(), qs.row_ptr.astype(np.int64)),
+                      shape=(nq, qs.dim))
+    evaluated = np.zeros(int(S["n_blocks"]), dtype=bool)
+    qi, ci = np.nonzero(valid & (prefix > 0))
+    order = np.argsort(terms[qi, ci], kind="stable")
+    qi, ci = qi[order], ci[order]
+    ts = terms[qi, ci]
+    starts = np.concatenate([[0], np.flatnonzero(np.diff(ts)) + 1, [len(ts)]])
+    for g0, g1 in zip(starts[:-1], starts[1:]):
+        t = int(ts[g0])
+        b0, b1 = int(lo[t]), int(lo[t + 1])
+        nb = b1 - b0
+        lens = np.diff(so[b0:b1 + 1])
+        row = np.repeat(np.arange(nb), lens)
+        s0, s1 = int(so[b0]), int(so[b1])
+        vals = (S["blk_m"][b0 + row].astype(np.float64)
+                + S["sum_code"][s0:s1].astype(np.float64) * S["blk_delta"][b0 + row].astype(np.float64))
+        M = sp.csr_matrix((vals, S["sum_term"][s0:s1].astype(np.int64), np.concatenate([[0], np.cumsum(lens)])),
+                          shape=(nb, qs.dim))
+        R = (M @ Q[qi[g0:g1]].T).toarray().astype(np.float32)
+        ordr = np.argsort(-R, axis=0, kind="stable")  # score desc, block asc on ties
+        p = prefix[qi[g0:g1], ci[g0:g1]].astype(np.int64)
+        take = np.arange(nb)[:, None] < p[None, :]
+        evaluated[b0 + ordr[take]] = True
+    eb = np.flatnonzero(evaluated)
+    doc_len = np.diff(S["row_ptr"].astype(np.int64))
+    n_docs = po[eb + 1] - po[eb]
+    first = np.repeat(po[eb] - np.concatenate([[0], np.cumsum(n_docs)[:-1]]), n_docs)
+    posts = S["postings"][np.arange(int(n_docs.sum())) + first]
+    total += float(8 * len(eb) + 20 * n_docs.sum() + 4 * doc_len[posts].sum())
+    return total
+
+
 def device_collection(torch, synth, n_docs, mean, chunk=2_000_000):
     """The document stream's rows 0 .. n_docs - 1 generated on the host in
     chunks (the next chunk drawn while the last one is copied) into device
@@ -188,6 +242,7 @@ def main():
     ap.add_argument("--knn-hf", type=float, default=0.5, help="heap_factor of the graph-building searches")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per serving rate")
     ap.add_argument("--n-docs", type=int, default=0, help="override the workload's document count")
+    ap.add_argument("--no-unique", action="store_true", help="skip the compulsory (unique) bytes of the batch")
     ap.add_argument("--probe", default=os.path.join(ROOT, "paper_2509_24815_amd", "probes", "probe_1m.npy"),
                     help="learned block-probe weights to evaluate beside the heap_factor rule ('' = skip)")
     args = ap.parse_args()
@@ -404,6 +459,20 @@ def main():
 
     plain_ids = out_ids.cpu().numpy().view(np.uint32).copy()  # results of the timed steps
 
+    # compulsory bytes of the batch at the chosen point (lower bound of the traffic)
+    serialized, unique = None, None
+    if not on_device and not args.no_unique:
+        tu = time.time()
+        from paper_2509_24815_amd import indexfile
+        serialized = ix.serialize()
+        stride = cut or binding.MAX_QUERY_NNZ
+        _, _, pref_t, _, _, term_t = ix.search(qcsr, k, cut, chosen, trace=True, prefix_stride=stride,
+                                               query_mass=qmass)
+        unique = unique_bytes(indexfile.sections(serialized), qs, term_t.cpu().numpy().view(np.uint32),
+                              pref_t.cpu().numpy().view(np.uint16), k)
+        log(f"[bench] compulsory bytes of the batch: {unique:.4e} ({unique / bytes_per_launch:.3f} of the "
+            f"algorithmic bytes; {time.time() - tu:.1f} s)")
+
     # query_cut x heap_factor grid (same batch, autotuned shape)
     grid = None
     if args.grid:
@@ -536,8 +605,8 @@ def main():
     if args.cpu_seconds > 0:
         import oracle
         oracle.build() if not os.path.exists(oracle._LIB_PATH) else None
-        log("[bench] CPU baseline: serializing the index for the oracle")
-        buf = ix.serialize()
+        log("[bench] CPU baseline: the serialized index for the oracle")
+        buf = serialized if serialized is not None else ix.serialize()
         ref = oracle.Index(buf)
         threads = os.cpu_count() or 1
         pilot = qs.subset(range(min(nq, 4 * threads)))
@@ -594,7 +663,10 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "traffic_frac": None if traffic is None else round(traffic / (ms_per_step / 1e3) / 1e9
                                                                            / PEAK_HBM_GBS, 4),
-                     "alg_bytes_per_launch": bytes_per_launch},
+                     "alg_bytes_per_launch": bytes_per_launch,
+                     "unique_bytes_per_launch": unique,
+                     "unique_frac": None if unique is None else round(unique / (ms_per_step / 1e3) / 1e9
+                                                                      / PEAK_HBM_GBS, 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -670,8 +670,9 @@ int run_terms(const uint64_t* d_rp, const uint32_t* d_w, uint32_t dim, uint32_t 
     {
         long double total = 0, run = 0;
         for (uint32_t t : P.order) total += (long double)P.t_n[t] * P.t_nb[t] + P.t_n[t];
-        // about 2.5e10 units run in ten seconds; builds shorter than ~40 s stay one launch
-        const int n_slices = total > 1e11L ? (int)std::min<long double>(64, total / 2.5e10L + 1) : 1;
+        // about 2.5e10 units run in ten seconds; at least two launches, so
+        // that every build goes through the same sliced path
+        const int n_slices = (int)std::min<long double>(64, std::max<long double>(2, total / 2.5e10L + 1));
         for (uint32_t w = 0; w < P.order.size(); ++w) {
             const uint32_t t = P.order[w];
             run += (long double)P.t_n[t] * P.t_nb[t] + P.t_n[t];
@@ -691,7 +692,7 @@ int run_terms(const uint64_t* d_rp, const uint32_t* d_w, uint32_t dim, uint32_t 
             hipLaunchKernelGGL(seismic_dev::k_build_terms, dim3(grid), dim3(seismic_dev::kBT), 0, nullptr, as);
             if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess)
                 return fail(SEISMIC_EHIP, "gpu build: kernel failed");
-            if (p->verbose && cuts.size() > 2)
+            if (p->verbose && cuts.size() > 3)
                 std::fprintf(stderr, "gpu build: lists %u..%u of %zu done (%.1f s)\n", cuts[sl], cuts[sl + 1],
                              P.order.size(),
                              std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
