@@ -243,6 +243,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per serving rate")
     ap.add_argument("--n-docs", type=int, default=0, help="override the workload's document count")
     ap.add_argument("--no-unique", action="store_true", help="skip the compulsory (unique) bytes of the batch")
+    ap.add_argument("--locality", action="store_true",
+                    help="also time the batch reordered so that queries sharing their first lists run together")
     ap.add_argument("--probe", default=os.path.join(ROOT, "paper_2509_24815_amd", "probes", "probe_1m.npy"),
                     help="learned block-probe weights to evaluate beside the heap_factor rule ('' = skip)")
     args = ap.parse_args()
@@ -459,6 +461,37 @@ def main():
 
     plain_ids = out_ids.cpu().numpy().view(np.uint32).copy()  # results of the timed steps
 
+    locality = None
+    if args.locality:
+        # queries sorted by their first two visited lists (largest entries,
+        # value desc then term asc): concurrent queries share lists and blocks
+        keys = []
+        for q in range(nq):
+            t, v = qs.row(q)
+            o = np.lexsort((t, -v.astype(np.float64)))[:2]
+            keys.append((int(t[o[0]]) if len(o) else -1, int(t[o[1]]) if len(o) > 1 else -1))
+        perm = sorted(range(nq), key=lambda q: keys[q])
+        pq = qs.subset(perm)
+        prp = torch.from_numpy(pq.row_ptr.astype(np.int64)).to(dev)
+        pw_ = torch.from_numpy(pq.words.view(np.int32)).to(dev)
+        pcsr = binding.device_csr(prp, pw_, pq.dim)
+        for _ in range(args.warmup):
+            binding.seismic_search_batch(ix.handle, ws, pcsr, k, cut, chosen, out_ids, out_sc, None, 0, None, stream,
+                                         query_mass=qmass)
+        torch.cuda.synchronize()
+        o0, o1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        o0.record(stream)
+        for _ in range(args.steps):
+            binding.seismic_search_batch(ix.handle, ws, pcsr, k, cut, chosen, out_ids, out_sc, None, 0, None, stream,
+                                         query_mass=qmass)
+        o1.record(stream)
+        torch.cuda.synchronize()
+        oms = o0.elapsed_time(o1) / args.steps
+        same = bool(np.array_equal(out_ids.cpu().numpy().view(np.uint32), plain_ids[perm]))
+        locality = {"ms_per_step": round(oms, 4), "qps": round(nq / (oms / 1e3), 1),
+                    "vs_batch_order": round(ms_per_step / oms, 4), "same_results": same}
+        log(f"[bench] locality order {locality}")
+
     # compulsory bytes of the batch at the chosen point (lower bound of the traffic)
     serialized, unique = None, None
     if not on_device and not args.no_unique:
@@ -657,7 +690,8 @@ def main():
                    ("device-resident" if on_device else "host" if args.host_build else "gpu"),
                    "hbm": hbm,
                    "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
-                   "sweep": sweep, "learned_probe": learned, "knn_refined": refined, "grid": grid},
+                   "sweep": sweep, "learned_probe": learned, "knn_refined": refined, "grid": grid,
+                   "locality_order": locality},
         "serving": serving,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
