@@ -1,10 +1,11 @@
 // Index build on the GPU (Algorithm "Indexing with Seismic", Section 4.4),
 // producing byte for byte the index the host builder produces.
 //
-// The host transposes the forward index (column lists, doc ascending) and
-// decides per term the kept count n = min(|L_i|, cap_i) and the block count
-// nb; everything else runs in one kernel, a workgroup per term pulled from a
-// queue (longest lists first):
+// The device transposes the forward index (column lists, doc ascending;
+// csc.hip), the host decides per term the kept count n = min(|L_i|, cap_i)
+// and the block count nb; everything else runs in one kernel, a workgroup
+// per term pulled from a queue (longest lists first), launched over slices
+// of that order:
 //   A. Set alpha-MSS: the n largest values of the column (value desc, doc
 //      asc) found by a two-level histogram over the fp16 bits, then a
 //      stream compaction in column order (so the kept list stays doc
@@ -19,9 +20,11 @@
 //   E. per block, the max vector phi over the block's rows, its gamma-MSS
 //      (value desc, term asc; the boundary found by two histograms of exact
 //      integer masses) and the u8 quantization on the 2^-14 grid.
-// Summaries go to a bump-allocated region; the host assembles the final
-// arrays in canonical order.  Capacities that a term would exceed set a flag
-// and the caller falls back to the host builder.
+// Summaries go to a bump-allocated region.  seismic_build_index_gpu
+// assembles the final arrays in canonical order on the host;
+// seismic_build_index_device gathers them on the device and leaves the
+// index there.  Capacities that a term would exceed set a flag: the first
+// falls back to the host builder, the second reports EINVAL.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
