@@ -229,6 +229,9 @@ def main():
     ap.add_argument("--index-cache", default=None, help="load the index from this file if present, else build and save")
     ap.add_argument("--plain-rows", action="store_true", help="search the forward rows in place (no block-major copies)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--schedule", type=int, default=None,
+                    help="fix the launch shape to 256 threads, 3 per CU, window 8 and this schedule (0 query-major, "
+                         "1 list-major) instead of autotuning")
     ap.add_argument("--host-build", action="store_true",
                     help="build the index on the host (default: the GPU build, byte-identical)")
     ap.add_argument("--alpha", type=float, default=0.0,
@@ -337,6 +340,9 @@ def main():
     q_nnz = np.diff(qs.row_ptr.astype(np.int64))
     ws = binding.seismic_workspace_create(ix.handle, nq, max(k, 100))
     binding.seismic_workspace_set_config(ws, 256, 0, 8)
+    if args.schedule is not None:
+        binding.seismic_workspace_set_config(ws, 256, 3, 8, args.schedule)
+        args.no_autotune = True
     out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     out_sc = torch.empty((nq, k), dtype=torch.float32, device=dev)
     cut = 0 if args.query_mass > 0 else W["cut"]
@@ -432,13 +438,16 @@ def main():
     bytes_per_launch = float(alg_bytes(cnt, q_nnz, k).sum())
 
     # launch shape for this batch: the library's autotuner times every shape
-    tuned = None
+    tuned = binding.seismic_workspace_get_config(ws, nq) if args.schedule is not None else None
     if not args.no_autotune:
         tt = time.time()
         res = binding.seismic_autotune(ix.handle, ws, qcsr, k, cut, chosen, out_ids, out_sc, reps=2, stream=stream)
         tuned = binding.seismic_workspace_get_config(ws, nq)
         log(f"[bench] autotuned over {len(res)} shapes in {time.time() - tt:.1f} s: {tuned} "
             f"({min(r[1] for r in res):.3f} ms; worst {max(r[1] for r in res):.3f} ms)")
+        for sched in sorted({r[0].get("schedule", 0) for r in res}):
+            best_s = min((r for r in res if r[0].get("schedule", 0) == sched), key=lambda r: r[1])
+            log(f"[bench]   schedule {sched}: best {best_s[0]} {best_s[1]:.3f} ms")
 
     # timed steps
     for _ in range(args.warmup):

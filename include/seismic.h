@@ -224,14 +224,20 @@ void seismic_workspace_free(seismic_workspace* ws);
 
 /* Launch shape of the persistent search kernel held by a workspace:
    threads per workgroup (256 or 512), resident workgroups per CU
-   (0 = as many as fit), and the speculation window (1..32 consecutive
-   blocks of a list gathered before their prune decisions are replayed in
-   order; results never depend on it).  EINVAL for unsupported shapes. */
+   (0 = as many as fit), the speculation window (1..32 consecutive blocks
+   of a list gathered before their prune decisions are replayed in order),
+   and the schedule: 0 query-major (a workgroup runs all cut lists of one
+   query), 1 list-major (one launch per cut position; the items of a
+   position are grouped by list, longest lists first, so that queries
+   visiting the same list run together and share its blocks in the caches;
+   each query's top-k is carried between positions; used when 1 <=
+   query_cut <= 64, else query-major).  Results never depend on the shape.
+   EINVAL for unsupported shapes. */
 typedef struct {
     uint32_t threads;
     uint32_t blocks_per_cu;
     uint32_t window;
-    uint32_t reserved;
+    uint32_t schedule;
 } seismic_launch_config;
 
 /* set_config applies cfg to every batch-size bucket; get_config returns the

@@ -59,7 +59,7 @@ class AdamParams(ctypes.Structure):
 
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32), ("window", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("schedule", ctypes.c_uint32)]
 
 
 class ServerParams(ctypes.Structure):
@@ -252,15 +252,16 @@ def seismic_workspace_free(ws):
         load().seismic_workspace_free(ws)
 
 
-def seismic_workspace_set_config(ws, threads: int = 256, blocks_per_cu: int = 0, window: int = 4):
-    c = LaunchConfig(threads, blocks_per_cu, window, 0)
+def seismic_workspace_set_config(ws, threads: int = 256, blocks_per_cu: int = 0, window: int = 4, schedule: int = 0):
+    """schedule: 0 query-major, 1 list-major (see seismic_launch_config)."""
+    c = LaunchConfig(threads, blocks_per_cu, window, schedule)
     _check(load().seismic_workspace_set_config(ws, ctypes.byref(c)))
 
 
 def seismic_workspace_get_config(ws, n_queries: int) -> dict:
     c = LaunchConfig()
     _check(load().seismic_workspace_get_config(ws, n_queries, ctypes.byref(c)))
-    return {"threads": c.threads, "blocks_per_cu": c.blocks_per_cu, "window": c.window}
+    return {"threads": c.threads, "blocks_per_cu": c.blocks_per_cu, "window": c.window, "schedule": c.schedule}
 
 
 def _params(k, query_cut, heap_factor, flags=0, probe=None, probe_tau=0.0, query_mass=0.0):
@@ -278,7 +279,8 @@ def seismic_autotune(handle, ws, queries: Csr, k: int, query_cut: int, heap_fact
     n = ctypes.c_uint32(0)
     _check(load().seismic_autotune(handle, ws, ctypes.byref(queries), ctypes.byref(p), _ptr(out_ids), _ptr(out_scores),
                                    reps, res, max_results, ctypes.byref(n), _stream_handle(stream)))
-    return [({"threads": r.cfg.threads, "blocks_per_cu": r.cfg.blocks_per_cu, "window": r.cfg.window}, r.ms)
+    return [({"threads": r.cfg.threads, "blocks_per_cu": r.cfg.blocks_per_cu, "window": r.cfg.window,
+              "schedule": r.cfg.schedule}, r.ms)
             for r in res[:n.value]]
 
 
@@ -397,7 +399,7 @@ def seismic_server_create(handle, k: int, query_cut: int, heap_factor: float, ma
     """probe (device tensor) must outlive the server."""
     sp = _params(k, query_cut, heap_factor, 0, probe, probe_tau)
     lc = LaunchConfig(0, 0, 0, 0) if not launch else LaunchConfig(launch["threads"], launch["blocks_per_cu"],
-                                                                  launch["window"], 0)
+                                                                  launch["window"], launch.get("schedule", 0))
     p = ServerParams(sp, max_batch, n_slots, max_batch_nnz or max(MAX_QUERY_NNZ, 256 * max_batch),
                      1 if use_graphs else 0, lc)
     s = ctypes.c_void_p()

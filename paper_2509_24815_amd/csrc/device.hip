@@ -25,8 +25,21 @@ void device_index_free(DeviceIndex* d) {
     (void)hipFree(d->xq_ptr);
     (void)hipFree(d->xq_words);
     (void)hipFree(d->knn);
+    (void)hipFree(d->term_rank);
     if (switched) (void)hipSetDevice(prev);
     delete d;
+}
+
+int device_term_rank(DeviceIndex* d, const std::vector<uint32_t>& list_off, uint32_t dim) {
+    std::vector<uint32_t> order(dim), rank(dim);
+    for (uint32_t t = 0; t < dim; ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        return list_off[x + 1] - list_off[x] > list_off[y + 1] - list_off[y];
+    });
+    for (uint32_t i = 0; i < dim; ++i) rank[order[i]] = i;
+    HIP_TRY(hipMalloc((void**)&d->term_rank, (size_t)dim * 4));
+    HIP_TRY(hipMemcpy(d->term_rank, rank.data(), (size_t)dim * 4, hipMemcpyHostToDevice));
+    return SEISMIC_OK;
 }
 
 namespace {
@@ -85,6 +98,8 @@ struct seismic_workspace {
     uint64_t* q_ptr = nullptr;  // staging for host-resident queries
     uint32_t* q_words = nullptr;
     size_t q_rows_cap = 0, q_words_cap = 0;
+    seismic_dev::ListSched ls;  // list-major schedule buffers (allocated on first request)
+    std::vector<void*> ls_allocs;
 };
 
 namespace {
@@ -95,6 +110,7 @@ int check_config(const seismic_workspace* ws, const seismic_launch_config* c) {
     if (c->threads != 256 && c->threads != 512) return fail(SEISMIC_EINVAL, "config: threads must be 256 or 512");
     if (c->window < 1 || c->window > seismic_dev::kMaxW)
         return fail(SEISMIC_EINVAL, "config: window must be in [1, %u]", seismic_dev::kMaxW);
+    if (c->schedule > 1) return fail(SEISMIC_EINVAL, "config: schedule must be 0 or 1");
     size_t smem = seismic_dev::search_smem_bytes(c->threads, ws->index->h.dim, ws->index->dev->sort_cap, ws->max_k);
     if (smem > ws->index->dev->smem_limit)
         return fail(SEISMIC_EINVAL, "config: %zu bytes of LDS needed, the device allows %zu", smem, ws->index->dev->smem_limit);
@@ -123,6 +139,31 @@ int check_params(const seismic_index* index, const seismic_workspace* ws, const 
 }
 
 // Enqueue one search of device-resident rows with launch shape cfg.
+// Buffers of the list-major schedule for the workspace's capacity.
+int ensure_list_sched(seismic_workspace* ws) {
+    if (ws->ls.cut) return SEISMIC_OK;
+    const size_t nq = std::max<uint32_t>(ws->max_queries, 1), k = ws->max_k, R = seismic_dev::kMaxRounds;
+    const uint32_t dim = ws->index->h.dim;
+    seismic_dev::ListSched l;
+    auto al = [&](auto*& p, size_t bytes) {
+        void* x = nullptr;
+        if (hipMalloc(&x, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
+        ws->ls_allocs.push_back(x);
+        p = (std::remove_reference_t<decltype(p)>)x;
+        return true;
+    };
+    bool ok = al(l.cut, nq * R * 2) && al(l.ncut, nq * 4) && al(l.hist, R * ((size_t)dim + 1) * 4) &&
+              al(l.items, nq * R * 4) && al(l.key0, nq * 4) && al(l.seg, (R + 1) * 4) && al(l.queues, (R + 1) * 4) &&
+              al(l.hs, nq * k * 4) && al(l.hid, nq * k * 4) && al(l.hn, nq * 4) && al(l.cnt, nq * 6 * 8);
+    if (!ok) {
+        for (void* x : ws->ls_allocs) (void)hipFree(x);
+        ws->ls_allocs.clear();
+        return fail(SEISMIC_ENOMEM, "workspace: list-major schedule buffers do not fit");
+    }
+    ws->ls = l;
+    return SEISMIC_OK;
+}
+
 int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64_t* q_ptr, const uint32_t* q_words,
                  uint64_t nq, uint64_t nnz, const seismic_search_params* params, uint32_t* out_ids, float* out_scores,
                  const seismic_stats* stats, const seismic_launch_config& cfg, hipStream_t st,
@@ -160,7 +201,14 @@ int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64
     if (per_cu < 1) return fail(SEISMIC_EHIP, "search: kernel does not fit on a CU (%zu bytes of LDS)", smem);
     if (cfg.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)cfg.blocks_per_cu);
     uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ws->n_cu, nq);
-    HIP_TRY(seismic_dev::launch_search(a, nt, grid, smem, st));
+    if (cfg.schedule == 1 && ws->ls.cut && index->dev->term_rank && params->query_cut >= 1 &&
+        params->query_cut <= seismic_dev::kMaxRounds) {
+        seismic_dev::ListSched ls = ws->ls;
+        ls.term_rank = index->dev->term_rank;
+        HIP_TRY(seismic_dev::launch_search_rounds(a, ls, nt, grid, smem, st));
+    } else {
+        HIP_TRY(seismic_dev::launch_search(a, nt, grid, smem, st));
+    }
     if (params->flags & SEISMIC_SEARCH_KNN) {
         seismic_dev::RefineArgs r{};
         r.ix = a.ix;
@@ -326,6 +374,7 @@ int seismic_index_upload(seismic_index* index, int device, uint32_t flags) {
     if (!rc) rc = upload_vec(d, h.sum_term, v.sum_term, 16);
     if (!rc) rc = upload_vec(d, h.sum_code, v.sum_code, 16);
     if (!rc && (flags & SEISMIC_UPLOAD_BLOCK_ROWS)) rc = build_block_rows(d, h);
+    if (!rc) rc = device_term_rank(d, h.list_off, h.dim);
     if (rc) { device_index_free(d); return rc; }
     v.dim = h.dim;
     v.n_docs = (uint32_t)h.n_docs;
@@ -371,12 +420,17 @@ void seismic_workspace_free(seismic_workspace* ws) {
     (void)hipFree(ws->probe_w);
     (void)hipFree(ws->q_ptr);
     (void)hipFree(ws->q_words);
+    for (void* x : ws->ls_allocs) (void)hipFree(x);
     delete ws;
 }
 
 int seismic_workspace_set_config(seismic_workspace* ws, const seismic_launch_config* cfg) {
     if (!ws || !cfg) return fail(SEISMIC_EINVAL, "config: null argument");
     int rc = check_config(ws, cfg);
+    if (!rc && cfg->schedule == 1) {
+        DeviceGuard g(ws->device);
+        rc = g.ok() ? ensure_list_sched(ws) : fail(SEISMIC_EHIP, "config: cannot select device");
+    }
     if (rc) return rc;
     for (auto& c : ws->cfg) c = *cfg;
     return SEISMIC_OK;
@@ -442,13 +496,17 @@ int seismic_autotune(const seismic_index* index, seismic_workspace* ws, const se
     uint32_t count = 0;
     bool have_ref = false;
     int err = SEISMIC_OK;
+    // the list-major schedule is tried when it applies and its buffers fit
+    const bool lists = params->query_cut >= 1 && params->query_cut <= seismic_dev::kMaxRounds &&
+                       index->dev->term_rank && ensure_list_sched(ws) == SEISMIC_OK;
+    for (uint32_t sched = 0; sched <= (lists ? 1u : 0u) && !err; ++sched)
     for (uint32_t nt : {256u, 512u}) {
         size_t smem = seismic_dev::search_smem_bytes(nt, index->h.dim, index->dev->sort_cap, params->k);
         if (smem > index->dev->smem_limit) continue;
         const int max_pc = seismic_dev::search_blocks_per_cu(nt, smem);
         for (int pc = 1; pc <= max_pc && !err; ++pc) {
             for (uint32_t w : {1u, 2u, 4u, 8u, 16u}) {
-                seismic_launch_config c{nt, (uint32_t)pc, w, 0};
+                seismic_launch_config c{nt, (uint32_t)pc, w, sched};
                 // warm-up run, then compare its results with the first shape's
                 err = launch_batch(index, ws, queries->row_ptr, queries->words, queries->n_rows, queries->nnz, params,
                                    out_ids, out_scores, nullptr, c, st);
@@ -461,7 +519,7 @@ int seismic_autotune(const seismic_index* index, seismic_workspace* ws, const se
                 }
                 if (have_ref && (std::memcmp(ids.data(), ref_ids.data(), n_out * 4) != 0 ||
                                  std::memcmp(sc.data(), ref_sc.data(), n_out * 4) != 0)) {
-                    err = fail(SEISMIC_ESTATE, "autotune: results differ between launch shapes (threads %u, per CU %d, window %u)", nt, pc, w);
+                    err = fail(SEISMIC_ESTATE, "autotune: results differ between launch shapes (threads %u, per CU %d, window %u, schedule %u)", nt, pc, w, sched);
                     break;
                 }
                 have_ref = true;

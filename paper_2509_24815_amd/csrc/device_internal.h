@@ -32,7 +32,13 @@ struct DeviceIndex {
     // kappa-NN graph [n_docs * kappa] (optional)
     uint32_t* knn = nullptr;
     uint32_t kappa = 0;
+    // [dim] rank of every list by block count (descending, then term):
+    // the order of the list-major schedule's items
+    uint32_t* term_rank = nullptr;
 };
+
+// Fills d->term_rank from the list offsets (host) of the index.
+int device_term_rank(DeviceIndex* d, const std::vector<uint32_t>& list_off, uint32_t dim);
 
 // Makes a device current for the lifetime of the object.
 class DeviceGuard {

@@ -1022,6 +1022,8 @@ extern "C" int seismic_build_index_device(const seismic_csr* docs, const seismic
         return bail(fail(SEISMIC_EHIP, "device build: forward index copy failed"));
     v.dim = dim;
     v.n_docs = (uint32_t)n_docs;
+    rc = device_term_rank(d, H.list_off, dim);
+    if (rc) return bail(rc);
     if (p->verbose) std::fprintf(stderr, "device build: done (%.1f s)\n", elapsed());
     *out = ix;
     return SEISMIC_OK;

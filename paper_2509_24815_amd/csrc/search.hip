@@ -369,14 +369,44 @@ struct Counters {
     uint64_t sum = 0, blocks = 0, eval = 0, docs = 0, tests = 0, nnz = 0;
 };
 
-// Steps 2a-2c for every cut list of query qi.
+// List-major schedule: the top-k and counters a query carries from one cut
+// position to the next.
+__device__ __forceinline__ uint32_t carry_in(const SearchArgs& a, float* s0, uint32_t* i0, uint32_t qi) {
+    const uint32_t hn = a.ls_hn[qi];
+    for (uint32_t i = threadIdx.x; i < hn; i += blockDim.x) {
+        s0[i] = a.ls_hs[(size_t)qi * a.k + i];
+        i0[i] = a.ls_hid[(size_t)qi * a.k + i];
+    }
+    return hn;
+}
+
+// Adds the counters of the earlier positions (thread 0's C and nnz); if
+// the query has later positions, stores its top-k and counters for them.
+__device__ __forceinline__ void carry_out(const SearchArgs& a, const float* H, const uint32_t* I, uint32_t hn,
+                                       uint32_t qi, bool last, Counters& C, unsigned long long& nnz) {
+    uint64_t* cc = a.ls_cnt + (size_t)qi * 6;
+    if (a.round > 0 && threadIdx.x == 0) {
+        C.sum += cc[0]; C.blocks += cc[1]; C.eval += cc[2]; C.docs += cc[3]; nnz += cc[4]; C.tests += cc[5];
+    }
+    if (last) return;
+    for (uint32_t i = threadIdx.x; i < hn; i += blockDim.x) {
+        a.ls_hs[(size_t)qi * a.k + i] = H[i];
+        a.ls_hid[(size_t)qi * a.k + i] = I[i];
+    }
+    if (threadIdx.x == 0) {
+        a.ls_hn[qi] = hn;
+        cc[0] = C.sum; cc[1] = C.blocks; cc[2] = C.eval; cc[3] = C.docs; cc[4] = nnz; cc[5] = C.tests;
+    }
+}
+
+// Steps 2a-2c for the cut lists ci0 .. ci1 - 1 of query qi.
 template <int NT, typename Look>
-__device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>& top, const Look& look, uint32_t qi,
-                          uint32_t ncut, uint32_t nvalid, Counters& C) {
+__device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>& top, const Look& look, uint32_t qi,
+                          uint32_t ci0, uint32_t ci1, uint32_t nvalid, Counters& C) {
     const int tid = threadIdx.x;
     const DevIdx& ix = a.ix;
     const uint32_t W = a.window;
-    for (uint32_t ci = 0; ci < ncut; ++ci) {
+    for (uint32_t ci = ci0; ci < ci1; ++ci) {
         const uint32_t t = L.cut[ci];
         const uint32_t b0 = ix.list_off[t], b1 = ix.list_off[t + 1];
         const uint32_t nb = b1 - b0;
@@ -550,8 +580,12 @@ __device__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>&
     }
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
+// LIST: the list-major schedule's round kernel (a separate instance, so that
+// the query-major kernel carries none of its code; its carry code would
+// take it past three workgroups per CU, so the bound keeps three and the
+// compiler spills a few values of that code).
+template <int NT, bool LIST>
+__global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(SearchArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int tid = threadIdx.x;
     const DevIdx& ix = a.ix;
@@ -564,12 +598,20 @@ __global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
     __syncthreads();
 
     const uint32_t nq = a.nq_dev ? min(*a.nq_dev, a.nq) : a.nq;
+    // work items: queries, or in a list-major round the queries holding a
+    // cut list at this position
+    uint32_t it0 = 0, n_items = nq;
+    if constexpr (LIST) {
+        it0 = a.ls_seg[a.round];
+        n_items = a.ls_seg[a.round + 1] - it0;
+    }
     for (;;) {
         // ------------------------------------------------ next query
         if (tid == 0) L.misc[15] = atomicAdd(a.queue, 1u);
         __syncthreads();
-        const uint32_t qi = L.misc[15];
-        if (qi >= nq) break;
+        const uint32_t item = __builtin_amdgcn_readfirstlane(L.misc[15]);
+        if (item >= n_items) break;
+        const uint32_t qi = __builtin_amdgcn_readfirstlane(LIST ? a.ls_items[it0 + item] : item);
         top.which = 0;
         top.hn = 0;
 
@@ -608,7 +650,7 @@ __global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
         if (nvalid_local) atomicAdd(&L.misc[1], nvalid_local);
         if (a.qmass > 0.0 && mass_local != 0.0) atomicAdd((double*)&L.misc[8], mass_local);
         __syncthreads();
-        const uint32_t nvalid = L.misc[1];
+        const uint32_t nvalid = __builtin_amdgcn_readfirstlane(L.misc[1]);
         const bool u8mode = nvalid <= kMaxSlots;
         const uint32_t ncut0 = (a.cut == 0 || a.cut > nvalid) ? nvalid : a.cut;
         const double mass_target = a.qmass * *(const double*)&L.misc[8];
@@ -648,9 +690,9 @@ __global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
             if (a.qmass > 0.0 && before < mass_target) ++in_mss;
         }
         if (in_mss) atomicAdd(&L.misc[10], in_mss);
-        const uint32_t status = L.misc[0];
+        const uint32_t status = __builtin_amdgcn_readfirstlane(L.misc[0]);
         __syncthreads();
-        const uint32_t ncut = a.qmass > 0.0 ? min(ncut0, L.misc[10]) : ncut0;
+        const uint32_t ncut = __builtin_amdgcn_readfirstlane(a.qmass > 0.0 ? min(ncut0, L.misc[10]) : ncut0);
         if (u8mode) {
             // bitmap + prefix -> slot table
             for (uint32_t i = tid; i < (10 * nw + 15) / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
@@ -665,17 +707,45 @@ __global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
         }
         __syncthreads();
 
+        uint32_t ci0 = 0, ci1 = ncut;
+        bool last = true;
+        if constexpr (LIST) {
+            ci0 = min(a.round, ncut);
+            ci1 = min(a.round + 1, ncut);
+            last = a.round + 1 >= ncut;
+            if (a.round > 0) {  // the top-k carried from the previous position
+                top.hn = carry_in(a, top.s0, top.i0, qi);
+                __syncthreads();
+            }
+        }
+
         Counters C;
         if (u8mode) {
             LookU8 look{L.region, L.qv};
-            run_lists<NT, LookU8>(a, L, top, look, qi, ncut, nvalid, C);
+            run_lists<NT, LookU8>(a, L, top, look, qi, ci0, ci1, nvalid, C);
         } else {
             LookBits look{L.bq};
-            run_lists<NT, LookBits>(a, L, top, look, qi, ncut, nvalid, C);
+            run_lists<NT, LookBits>(a, L, top, look, qi, ci0, ci1, nvalid, C);
+        }
+        unsigned long long nnz_tot = 0;
+        if (a.counters || LIST) {
+            const unsigned long long v = wave_sum((unsigned long long)C.nnz);
+            unsigned long long* red = (unsigned long long*)L.crs;  // union region is free here
+            if ((tid & (kWave - 1)) == 0) red[tid / kWave] = v;
+            __syncthreads();
+            for (int w = 0; w < NT / kWave; ++w) nnz_tot += red[w];
+            __syncthreads();
+        }
+        if constexpr (LIST) {
+            carry_out(a, top.hs(), top.hid(), top.hn, qi, last, C, nnz_tot);
+            if (a.round == 0) {  // the cut lists, for the items of the later positions
+                if ((uint32_t)tid < ncut) a.ls_cut[(size_t)qi * a.cmax + tid] = L.cut[tid];
+                if (tid == 0) a.ls_ncut[qi] = ncut;
+            }
         }
 
         // ------------------------------------------------------------ output
-        {
+        if (last) {
             const float* H = top.hs();
             const uint32_t* I = top.hid();
             for (uint32_t i = tid; i < a.k; i += NT) {
@@ -683,22 +753,14 @@ __global__ __launch_bounds__(NT) void k_search(SearchArgs a) {
                 a.out_ids[(size_t)qi * a.k + i] = have ? I[i] : 0xFFFFFFFFu;
                 a.out_scores[(size_t)qi * a.k + i] = have ? H[i] : -INFINITY;
             }
-        }
-        for (uint32_t i = ncut + tid; i < a.prefix_stride; i += NT) {
-            if (a.prefix) a.prefix[(size_t)qi * a.prefix_stride + i] = 0;
-            if (a.list_term) a.list_term[(size_t)qi * a.prefix_stride + i] = 0xFFFFFFFFu;
-            if (a.list_hmin) a.list_hmin[(size_t)qi * a.prefix_stride + i] = -1.0f;
-        }
-        if (a.counters) {
-            const unsigned long long v = wave_sum((unsigned long long)C.nnz);
-            unsigned long long* red = (unsigned long long*)L.crs;  // union region is free here
-            if ((tid & (kWave - 1)) == 0) red[tid / kWave] = v;
-            __syncthreads();
-            if (tid == 0) {
-                unsigned long long tot = 0;
-                for (int w = 0; w < NT / kWave; ++w) tot += red[w];
+            for (uint32_t i = ncut + tid; i < a.prefix_stride; i += NT) {
+                if (a.prefix) a.prefix[(size_t)qi * a.prefix_stride + i] = 0;
+                if (a.list_term) a.list_term[(size_t)qi * a.prefix_stride + i] = 0xFFFFFFFFu;
+                if (a.list_hmin) a.list_hmin[(size_t)qi * a.prefix_stride + i] = -1.0f;
+            }
+            if (a.counters && tid == 0) {
                 uint64_t* c = a.counters + (size_t)qi * 8;
-                c[0] = C.sum; c[1] = C.blocks; c[2] = C.eval; c[3] = C.docs; c[4] = tot; c[5] = C.tests;
+                c[0] = C.sum; c[1] = C.blocks; c[2] = C.eval; c[3] = C.docs; c[4] = nnz_tot; c[5] = C.tests;
                 c[6] = status; c[7] = ncut;
             }
         }
@@ -719,14 +781,99 @@ __global__ void k_reset_queue(uint32_t* queue) {
     if (threadIdx.x == 0) *queue = 0;
 }
 
+// ----------------------------------------------- list-major schedule items
+// Items are sorted by a key per (query, cut position): the rank of the
+// position's list among all lists by block count (longest first), or dim
+// for a query with no cut list (one item at position 0, which writes its
+// empty result).  Counting sort over rows hist[r * (dim + 1) + key].
+// Position 0's keys come from each query's largest entry (its first cut
+// list); the later positions' from the cut lists that position 0 records.
+
+__global__ __launch_bounds__(256) void k_items_zero(uint32_t* hist, uint32_t n) {
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) hist[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_items_first(const uint32_t* nq_dev, uint32_t nq, const uint64_t* q_ptr,
+                                                     const uint32_t* q_words, uint64_t q_nnz, uint32_t dim,
+                                                     const uint32_t* term_rank, uint32_t* key0, uint32_t* hist) {
+    const uint32_t n = nq_dev ? min(*nq_dev, nq) : nq;
+    const uint32_t q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const uint64_t q1 = min(q_ptr[q + 1], q_nnz), q0 = min(q_ptr[q], q1);
+    uint32_t bt = 0xFFFFFFFFu, bh = 0;
+    for (uint64_t j = q0; j < min(q1, q0 + kMaxQ); ++j) {
+        const uint32_t w = q_words[j], t = w & 0xFFFFu, h = w >> 16;
+        if (t >= dim || !half_ok(h)) continue;
+        if (bt == 0xFFFFFFFFu || h > bh || (h == bh && t < bt)) { bt = t; bh = h; }
+    }
+    const uint32_t key = bt == 0xFFFFFFFFu ? dim : term_rank[bt];
+    key0[q] = key;
+    atomicAdd(&hist[key], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_items_count(const uint32_t* nq_dev, uint32_t nq, uint32_t cmax, uint32_t dim,
+                                                     const uint16_t* cut, const uint32_t* ncut,
+                                                     const uint32_t* term_rank, uint32_t* hist) {
+    const uint32_t n = nq_dev ? min(*nq_dev, nq) : nq;
+    const uint32_t q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const uint32_t c = min(ncut[q], cmax);
+    for (uint32_t r = 1; r < c; ++r) atomicAdd(&hist[r * (dim + 1) + term_rank[cut[(size_t)q * cmax + r]]], 1u);
+}
+
+// Exclusive scan of rows [row0, row1) of hist in place (one workgroup),
+// starting at seg[row0] (0 for row 0); seg[r] = first item of position r for
+// r in [row0, row1]; the positions' queues zeroed.
+__global__ __launch_bounds__(1024) void k_items_scan(uint32_t* hist, uint32_t row0, uint32_t row1, uint32_t dim,
+                                                     uint32_t* seg, uint32_t* queues) {
+    __shared__ uint32_t part[1024];
+    const uint32_t tid = threadIdx.x, w = dim + 1, b = row0 * w, n = (row1 - row0) * w;
+    const uint32_t base = row0 == 0 ? 0u : seg[row0];
+    const uint32_t per = (n + 1023) / 1024, lo = min(n, tid * per), hi = min(n, lo + per);
+    uint32_t sum = 0;
+    for (uint32_t i = lo; i < hi; ++i) sum += hist[b + i];
+    part[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = base;
+        for (uint32_t i = 0; i < 1024; ++i) { const uint32_t v = part[i]; part[i] = run; run += v; }
+        seg[row1] = run;
+    }
+    __syncthreads();
+    uint32_t run = part[tid];
+    for (uint32_t i = lo; i < hi; ++i) {
+        if (i % w == 0) seg[row0 + i / w] = run;
+        const uint32_t v = hist[b + i];
+        hist[b + i] = run;
+        run += v;
+    }
+    for (uint32_t r = row0 + tid; r < row1; r += 1024) queues[r] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_items_scatter(const uint32_t* nq_dev, uint32_t nq, uint32_t cmax,
+                                                       uint32_t dim, const uint16_t* cut, const uint32_t* ncut,
+                                                       const uint32_t* term_rank, const uint32_t* key0,
+                                                       uint32_t* hist, uint32_t* items) {
+    const uint32_t n = nq_dev ? min(*nq_dev, nq) : nq;
+    const uint32_t q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    if (key0) {  // position 0
+        items[atomicAdd(&hist[key0[q]], 1u)] = q;
+        return;
+    }
+    const uint32_t c = min(ncut[q], cmax);
+    for (uint32_t r = 1; r < c; ++r)
+        items[atomicAdd(&hist[r * (dim + 1) + term_rank[cut[(size_t)q * cmax + r]]], 1u)] = q;
+}
+
 size_t search_smem_bytes(uint32_t nt, uint32_t dim, uint32_t sort_cap, uint32_t k) {
     return nt == 512 ? search_smem_bytes_t<512>(dim, sort_cap, k) : search_smem_bytes_t<256>(dim, sort_cap, k);
 }
 
 int search_blocks_per_cu(uint32_t nt, size_t smem) {
     int n = 0;
-    hipError_t e = nt == 512 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<512>, 512, smem)
-                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<256>, 256, smem);
+    hipError_t e = nt == 512 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<512, false>, 512, smem)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<256, false>, 256, smem);
     return e == hipSuccess ? n : 0;
 }
 
@@ -734,10 +881,53 @@ hipError_t launch_search(const SearchArgs& a, uint32_t nt, uint32_t grid, size_t
     if (a.nq == 0) return hipSuccess;
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, stream, a.queue);
     if (nt == 512)
-        hipLaunchKernelGGL(k_search<512>, dim3(grid), dim3(512), smem, stream, a);
+        hipLaunchKernelGGL((k_search<512, false>), dim3(grid), dim3(512), smem, stream, a);
     else
-        hipLaunchKernelGGL(k_search<256>, dim3(grid), dim3(256), smem, stream, a);
+        hipLaunchKernelGGL((k_search<256, false>), dim3(grid), dim3(256), smem, stream, a);
     return hipGetLastError();
+}
+
+hipError_t launch_search_rounds(SearchArgs a, const ListSched& ls, uint32_t nt, uint32_t grid, size_t smem,
+                                hipStream_t stream) {
+    if (a.nq == 0) return hipSuccess;
+    const uint32_t cmax = a.cut, dim = a.ix.dim, qb = (a.nq + 255) / 256;
+    a.mode = kModeList;
+    a.cmax = cmax;
+    a.ls_cut = ls.cut;
+    a.ls_ncut = ls.ncut;
+    a.ls_items = ls.items;
+    a.ls_seg = ls.seg;
+    a.ls_hs = ls.hs;
+    a.ls_hid = ls.hid;
+    a.ls_hn = ls.hn;
+    a.ls_cnt = ls.cnt;
+    const uint32_t hn = cmax * (dim + 1);
+    auto round = [&](uint32_t r) {
+        a.round = r;
+        a.queue = ls.queues + r;
+        if (nt == 512)
+            hipLaunchKernelGGL((k_search<512, true>), dim3(grid), dim3(512), smem, stream, a);
+        else
+            hipLaunchKernelGGL((k_search<256, true>), dim3(grid), dim3(256), smem, stream, a);
+        return hipGetLastError();
+    };
+    hipLaunchKernelGGL(k_items_zero, dim3(std::min<uint32_t>(1024, (hn + 255) / 256)), dim3(256), 0, stream, ls.hist, hn);
+    hipLaunchKernelGGL(k_items_first, dim3(qb), dim3(256), 0, stream, a.nq_dev, a.nq, a.q_ptr, a.q_words, a.q_nnz, dim,
+                       ls.term_rank, ls.key0, ls.hist);
+    hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, stream, ls.hist, 0u, 1u, dim, ls.seg, ls.queues);
+    hipLaunchKernelGGL(k_items_scatter, dim3(qb), dim3(256), 0, stream, a.nq_dev, a.nq, cmax, dim, ls.cut, ls.ncut,
+                       ls.term_rank, ls.key0, ls.hist, ls.items);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = round(0);
+    if (e != hipSuccess || cmax < 2) return e;
+    hipLaunchKernelGGL(k_items_count, dim3(qb), dim3(256), 0, stream, a.nq_dev, a.nq, cmax, dim, ls.cut, ls.ncut,
+                       ls.term_rank, ls.hist);
+    hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, stream, ls.hist, 1u, cmax, dim, ls.seg, ls.queues);
+    hipLaunchKernelGGL(k_items_scatter, dim3(qb), dim3(256), 0, stream, a.nq_dev, a.nq, cmax, dim, ls.cut, ls.ncut,
+                       ls.term_rank, (const uint32_t*)nullptr, ls.hist, ls.items);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (uint32_t r = 1; r < cmax && e == hipSuccess; ++r) e = round(r);
+    return e;
 }
 
 }  // namespace seismic_dev
