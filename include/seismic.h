@@ -166,9 +166,9 @@ int seismic_build_index(const seismic_csr* docs, const seismic_build_params* par
    [2^-6, 2^6] every inner product of the assignment is exact, so the index
    is byte for byte the host build's.  Lists beyond the GPU path's
    capacities (more than 1024 blocks or 2^24 kept postings in one list)
-   make it fall back to seismic_build_index.  Synchronous; host documents
-   (on_device = 0); the index is returned in host memory like
-   seismic_build_index's (upload it to search). */
+   return EINVAL: build such an index with seismic_build_index.
+   Synchronous; host documents (on_device = 0); the index is returned in
+   host memory like seismic_build_index's (upload it to search). */
 int seismic_build_index_gpu(const seismic_csr* docs, const seismic_build_params* params, int device,
                             seismic_index** out);
 
@@ -183,8 +183,8 @@ int seismic_build_index_gpu(const seismic_csr* docs, const seismic_build_params*
    6 bytes per nonzero of column lists, and the kept lists and summaries.
    serialize/save copy the index back to the host; upload returns ESTATE.
    The same results as seismic_build_index_gpu, byte for byte.  Lists
-   beyond the capacities above return EINVAL (no host fallback); ENOMEM
-   when device memory runs out.  Synchronous. */
+   beyond the capacities above return EINVAL; ENOMEM when device memory
+   runs out.  Synchronous. */
 int seismic_build_index_device(const seismic_csr* docs, const seismic_build_params* params, int device,
                                seismic_index** out);
 

@@ -23,8 +23,8 @@
 // Summaries go to a bump-allocated region.  seismic_build_index_gpu
 // assembles the final arrays in canonical order on the host;
 // seismic_build_index_device gathers them on the device and leaves the
-// index there.  Capacities that a term would exceed set a flag: the first
-// falls back to the host builder, the second reports EINVAL.
+// index there.  A term beyond the kernel's capacities makes either report
+// EINVAL (the host builder has no such limits).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -864,8 +864,8 @@ extern "C" int seismic_build_index_gpu(const seismic_csr* docs, const seismic_bu
     if (!plan_fits(P)) {
         csc.release();
         delete ix;
-        if (p->verbose) std::fprintf(stderr, "gpu build: lists beyond the GPU path's limits; building on the host\n");
-        return seismic_build_index(docs, p, out);
+        return fail(SEISMIC_EINVAL, "gpu build: a list needs %u blocks or %u postings (the GPU build handles %u and %u); "
+                    "build it with seismic_build_index", P.nb_max, P.n_max, kMaxNb, 1u << 24);
     }
     if (p->verbose) std::fprintf(stderr, "gpu build: column lists on the device (%.1f s)\n", elapsed());
     BuildArgs a;
@@ -876,8 +876,8 @@ extern "C" int seismic_build_index_gpu(const seismic_csr* docs, const seismic_bu
     if (rc) { delete ix; return rc; }
     if (flags) {
         delete ix;
-        if (p->verbose) std::fprintf(stderr, "gpu build: a list exceeded the GPU path's capacities (%u); building on the host\n", flags);
-        return seismic_build_index(docs, p, out);
+        return fail(SEISMIC_EINVAL, "gpu build: a list exceeded the kernel's capacities (%u); build it with "
+                    "seismic_build_index", flags);
     }
     if (p->verbose) std::fprintf(stderr, "gpu build: lists, blocks and summaries on the device (%.1f s)\n", elapsed());
     // assemble the host index in canonical order

@@ -18,12 +18,9 @@ def _log(msg):
     print(msg, flush=True)
 
 
-def _same(docs, capfd, **kw):
+def _same(docs, **kw):
     h = Index.build(docs, seed=kw.get("seed", 0), **{k: v for k, v in kw.items() if k != "seed"})
-    capfd.readouterr()
     g = Index.build_gpu(docs, seed=kw.get("seed", 0), verbose=True, **{k: v for k, v in kw.items() if k != "seed"})
-    err = capfd.readouterr().err
-    assert "building on the host" not in err, err  # the GPU path itself ran
     hb, gb = h.serialize(), g.serialize()
     assert hb.size == gb.size
     if not np.array_equal(hb, gb):
@@ -40,21 +37,21 @@ def _same(docs, capfd, **kw):
     (5000, 100000, 10, 0.4, 0.0),     # nothing truncated
     (40000, 150, 150, 0.4, 0.0),      # a block per document in full lists
 ])
-def test_gpu_build_equals_host_build(capfd, n, lam, beta, gamma, alpha):
+def test_gpu_build_equals_host_build(n, lam, beta, gamma, alpha):
     _log(f"[gpu build] n={n} lambda={lam} beta={beta} gamma={gamma} alpha={alpha}")
     docs = synth.docs(n, seed=n % 101)
-    g = _same(docs, capfd, lam=lam, beta=beta, gamma=gamma, alpha=alpha, seed=7)
+    g = _same(docs, lam=lam, beta=beta, gamma=gamma, alpha=alpha, seed=7)
     assert oracle.Index(g.serialize()).check(clustering=True, term_stride=5) == ""
 
 
-def test_gpu_build_ties_and_tiny_collections(capfd):
+def test_gpu_build_ties_and_tiny_collections():
     # every value equal: ties at every selection and summary boundary
     rows = [{t: 1.0 for t in range(i % 7, 60 + i % 13, 1 + i % 3)} for i in range(3000)]
     docs = synth.make_csr(rows, dim=128)
-    _same(docs, capfd, lam=200, beta=20, gamma=0.5)
+    _same(docs, lam=200, beta=20, gamma=0.5)
     # a handful of documents, some columns with a single entry
     small = synth.make_csr([{0: 2.0, 5: 1.0}, {5: 3.0}, {1: 0.5, 5: 0.5}, {7: 1.0}], dim=16)
-    _same(small, capfd, lam=2, beta=2, gamma=0.4)
+    _same(small, lam=2, beta=2, gamma=0.4)
 
 
 def _on_device(docs):
@@ -122,3 +119,17 @@ def test_device_build_edges_and_errors():
     with pytest.raises(SeismicError) as e:
         Index.build_device(short, lam=100, beta=10, gamma=0.4)
     assert e.value.code == binding.EINVAL
+
+
+def test_gpu_builds_refuse_lists_beyond_their_capacity():
+    # term 0 in every document: its list gets 1025 blocks, one more than the
+    # GPU build handles; neither GPU entry point falls back silently
+    rows = [{0: 0.02, d + 1: 1.0 + (d % 7) * 0.25} for d in range(3000)]
+    docs = synth.make_csr(rows, dim=3001)
+    with pytest.raises(SeismicError) as e:
+        Index.build_gpu(docs, lam=3000, beta=1025, gamma=0.4)
+    assert e.value.code == binding.EINVAL
+    with pytest.raises(SeismicError) as e:
+        Index.build_device(_on_device(docs), lam=3000, beta=1025, gamma=0.4)
+    assert e.value.code == binding.EINVAL
+    assert Index.build(docs, lam=3000, beta=1025, gamma=0.4).info()["max_blocks_per_list"] == 1025
