@@ -673,9 +673,9 @@ int run_terms(const uint64_t* d_rp, const uint32_t* d_w, uint32_t dim, uint32_t 
     {
         long double total = 0, run = 0;
         for (uint32_t t : P.order) total += (long double)P.t_n[t] * P.t_nb[t] + P.t_n[t];
-        // about 2.5e10 units run in ten seconds; at least two launches, so
-        // that every build goes through the same sliced path
-        const int n_slices = (int)std::min<long double>(64, std::max<long double>(2, total / 2.5e10L + 1));
+        // about 6e10 units run in twenty-five seconds; at least two launches,
+        // so that every build goes through the same sliced path
+        const int n_slices = (int)std::min<long double>(64, std::max<long double>(2, total / 6e10L + 1));
         for (uint32_t w = 0; w < P.order.size(); ++w) {
             const uint32_t t = P.order[w];
             run += (long double)P.t_n[t] * P.t_nb[t] + P.t_n[t];
