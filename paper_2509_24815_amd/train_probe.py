@@ -33,7 +33,7 @@ def main(argv=None):
     ap.add_argument("--pairs", type=int, default=500_000)
     ap.add_argument("--cut", type=int, default=10)
     ap.add_argument("--hf", type=float, default=0.8, help="heap_factor of the traced plain search")
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--neg-weight-per-doc", type=float, default=0.5)
