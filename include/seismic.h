@@ -232,7 +232,10 @@ void seismic_workspace_free(seismic_workspace* ws);
    visiting the same list run together and share its blocks in the caches;
    each query's top-k is carried between positions; used when 1 <=
    query_cut <= 64, else query-major).  Results never depend on the shape.
-   EINVAL for unsupported shapes. */
+   Selecting schedule 1 (set_config, or the autotuner trying it) allocates
+   the workspace's list-major buffers once: about max_queries * (390 + 8 *
+   max_k) bytes plus 256 bytes per index term.  EINVAL for unsupported
+   shapes, ENOMEM if those buffers do not fit. */
 typedef struct {
     uint32_t threads;
     uint32_t blocks_per_cu;
