@@ -233,7 +233,7 @@ void seismic_workspace_free(seismic_workspace* ws);
    each query's top-k is carried between positions; used when 1 <=
    query_cut <= 64, else query-major).  Results never depend on the shape.
    Selecting schedule 1 (set_config, or the autotuner trying it) allocates
-   the workspace's list-major buffers once: about max_queries * (390 + 8 *
+   the workspace's list-major buffers once: about max_queries * (450 + 8 *
    max_k) bytes plus 256 bytes per index term.  EINVAL for unsupported
    shapes, ENOMEM if those buffers do not fit. */
 typedef struct {
