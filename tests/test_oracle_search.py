@@ -189,3 +189,58 @@ def test_query_mass_cut_is_the_alpha_mss_of_the_query():
         assert r["counters"][0][7] == m
     r = ix.pruned_search(q, 5, 2, 0.8, c_cap=8, query_mass=1.0)  # query_cut still caps
     assert r["counters"][0][7] == 2
+
+
+# oracle switches (oracle.c): exact block summaries <q, phi(B)> over full
+# vectors, and a literal "continue" on a skipped block
+EXACT_SUMMARIES, CONTINUE = 1, 2
+
+
+@pytest.fixture(scope="module")
+def full_lists():
+    """Every list untruncated (lambda = the longest column), in blocks of
+    about eight documents."""
+    from paper_2509_24815_amd import Index
+    docs = synth.generate(1500, seed=21, stream=0, mean=25.0, lo=1, hi=80, dim=400)
+    qs = synth.generate(40, seed=21, stream=1, mean=8.0, lo=1, hi=40, dim=400)
+    lam = int(np.bincount(docs.terms(), minlength=400).max())  # the longest column: nothing truncated
+    ref = oracle.Index(Index.build(docs, lam=lam, beta=lam // 8, gamma=0.4, seed=3).serialize())
+    assert ref.check(clustering=True) == ""
+    return docs, qs, ref
+
+
+def test_no_pruning_is_exact_search(full_lists):
+    """hf = +inf, full lists, every query entry in the cut: Algorithm 2
+    evaluates every document with a shared term, so it is exact search."""
+    docs, qs, ref = full_lists
+    r = ref.pruned_search(qs, 10, 0, float("inf"))
+    e_ids, e_sc = oracle.exact_topk(docs, qs, 10)
+    assert np.array_equal(r["ids"], e_ids) and np.array_equal(r["scores"], e_sc)
+    d_ids, d_sc = _lexsort_topk((qs.dense() @ docs.dense().T).astype(np.float32), 10)
+    assert np.array_equal(r["ids"], d_ids) and np.array_equal(r["scores"], d_sc)
+
+
+def test_exact_summaries_make_the_rule_rank_safe(full_lists):
+    """With r_j = <q, phi(B_j)> (an upper bound of every score in the block)
+    and hf = 1, a skipped block holds no document that could enter the
+    heap: the result is the exact top-k while blocks are still skipped."""
+    docs, qs, ref = full_lists
+    e_ids, e_sc = oracle.exact_topk(docs, qs, 10)
+    r = ref.pruned_search(qs, 10, 0, 1.0, flags=EXACT_SUMMARIES)
+    assert np.array_equal(r["ids"], e_ids) and np.array_equal(r["scores"], e_sc)
+    full = ref.pruned_search(qs, 10, 0, float("inf"), flags=EXACT_SUMMARIES)
+    assert r["counters"][:, 2].sum() < full["counters"][:, 2].sum()  # the rule did prune
+
+
+@pytest.mark.parametrize("hf", [0.5, 0.8, 1.0, 1.5])
+def test_continue_and_stop_agree(full_lists, hf):
+    """Blocks are visited by summary score desc and the heap minimum never
+    decreases, so once a block fails the test every later block of the list
+    fails too: "continue" and "stop the list" evaluate the same blocks."""
+    docs, qs, ref = full_lists
+    for flags in (0, EXACT_SUMMARIES):
+        a = ref.pruned_search(qs, 10, 0, hf, flags=flags)
+        b = ref.pruned_search(qs, 10, 0, hf, flags=flags | CONTINUE)
+        assert np.array_equal(a["ids"], b["ids"]) and np.array_equal(a["scores"], b["scores"])
+        assert np.array_equal(a["prefix"], b["prefix"])
+        assert np.array_equal(a["counters"][:, :5], b["counters"][:, :5])
