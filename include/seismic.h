@@ -188,9 +188,17 @@ int seismic_build_index_gpu(const seismic_csr* docs, const seismic_build_params*
 int seismic_build_index_device(const seismic_csr* docs, const seismic_build_params* params, int device,
                                seismic_index** out);
 
-/* Serialized form (format version 1, little-endian): see DESIGN notes in
-   the source.  save writes a file; serialize writes into a caller buffer of
-   seismic_index_serialized_size() bytes.  EIO on write failure. */
+/* Serialized form (format version 1, little-endian): a 128-byte header
+   ("SEISMIC\0", u32 version, u32 dim, u64 n_docs, nnz, n_blocks,
+   n_postings, n_summary, u32 lambda, u32 beta, f64 gamma, u64 seed, u32
+   quantization grid bits, f64 alpha at offset 88), then 11 sections, each
+   at a 64-byte aligned offset: row_ptr u64[n_docs+1], words u32[nnz],
+   list_off u32[dim+1], blk_post_off u32[nb+1], blk_sum_off u64[nb+1],
+   blk_m f32[nb], blk_delta f32[nb], blk_centroid u32[nb], postings
+   u32[np], sum_term u16[ns], sum_code u8[ns].  save writes a file;
+   serialize writes into a caller buffer of seismic_index_serialized_size()
+   bytes (a device-built index is copied back from the device first).  EIO
+   on write failure. */
 int seismic_index_serialized_size(const seismic_index* index, uint64_t* bytes);
 int seismic_index_serialize(const seismic_index* index, void* buf, uint64_t bytes);
 int seismic_index_save(const seismic_index* index, const char* path);

@@ -142,7 +142,7 @@ int check_params(const seismic_index* index, const seismic_workspace* ws, const 
 // Buffers of the list-major schedule for the workspace's capacity.
 int ensure_list_sched(seismic_workspace* ws) {
     if (ws->ls.cut) return SEISMIC_OK;
-    const size_t nq = std::max<uint32_t>(ws->max_queries, 1), k = ws->max_k, R = seismic_dev::kMaxRounds;
+    const size_t nq = std::max<uint32_t>(ws->max_queries, 1), k = ws->max_k, R = seismic_dev::kMaxPositions;
     const uint32_t dim = ws->index->h.dim;
     seismic_dev::ListSched l;
     auto al = [&](auto*& p, size_t bytes) {
@@ -202,10 +202,10 @@ int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64
     if (cfg.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)cfg.blocks_per_cu);
     uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ws->n_cu, nq);
     if (cfg.schedule == 1 && ws->ls.cut && index->dev->term_rank && params->query_cut >= 1 &&
-        params->query_cut <= seismic_dev::kMaxRounds) {
+        params->query_cut <= seismic_dev::kMaxPositions) {
         seismic_dev::ListSched ls = ws->ls;
         ls.term_rank = index->dev->term_rank;
-        HIP_TRY(seismic_dev::launch_search_rounds(a, ls, nt, grid, smem, st));
+        HIP_TRY(seismic_dev::launch_search_positions(a, ls, nt, grid, smem, st));
     } else {
         HIP_TRY(seismic_dev::launch_search(a, nt, grid, smem, st));
     }
@@ -504,7 +504,7 @@ int seismic_autotune(const seismic_index* index, seismic_workspace* ws, const se
     bool have_ref = false;
     int err = SEISMIC_OK;
     // the list-major schedule is tried when it applies and its buffers fit
-    const bool lists = params->query_cut >= 1 && params->query_cut <= seismic_dev::kMaxRounds &&
+    const bool lists = params->query_cut >= 1 && params->query_cut <= seismic_dev::kMaxPositions &&
                        index->dev->term_rank && ensure_list_sched(ws) == SEISMIC_OK;
     for (uint32_t sched = 0; sched <= (lists ? 1u : 0u) && !err; ++sched)
     for (uint32_t nt : {256u, 512u}) {

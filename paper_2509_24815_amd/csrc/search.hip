@@ -385,7 +385,7 @@ __device__ __forceinline__ uint32_t carry_in(const SearchArgs& a, float* s0, uin
 __device__ __forceinline__ void carry_out(const SearchArgs& a, const float* H, const uint32_t* I, uint32_t hn,
                                        uint32_t qi, bool last, Counters& C, unsigned long long& nnz) {
     uint64_t* cc = a.ls_cnt + (size_t)qi * 6;
-    if (a.round > 0 && threadIdx.x == 0) {
+    if (a.pos > 0 && threadIdx.x == 0) {
         C.sum += cc[0]; C.blocks += cc[1]; C.eval += cc[2]; C.docs += cc[3]; nnz += cc[4]; C.tests += cc[5];
     }
     if (last) return;
@@ -580,7 +580,7 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
     }
 }
 
-// LIST: the list-major schedule's round kernel (a separate instance, so that
+// LIST: the list-major schedule's per-position kernel (a separate instance, so that
 // the query-major kernel carries none of its code; its carry code would
 // take it past three workgroups per CU, so the bound keeps three and the
 // compiler spills a few values of that code).
@@ -598,12 +598,12 @@ __global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(Sear
     __syncthreads();
 
     const uint32_t nq = a.nq_dev ? min(*a.nq_dev, a.nq) : a.nq;
-    // work items: queries, or in a list-major round the queries holding a
+    // work items: queries, or at a list-major position the queries holding a
     // cut list at this position
     uint32_t it0 = 0, n_items = nq;
     if constexpr (LIST) {
-        it0 = a.ls_seg[a.round];
-        n_items = a.ls_seg[a.round + 1] - it0;
+        it0 = a.ls_seg[a.pos];
+        n_items = a.ls_seg[a.pos + 1] - it0;
     }
     for (;;) {
         // ------------------------------------------------ next query
@@ -710,10 +710,10 @@ __global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(Sear
         uint32_t ci0 = 0, ci1 = ncut;
         bool last = true;
         if constexpr (LIST) {
-            ci0 = min(a.round, ncut);
-            ci1 = min(a.round + 1, ncut);
-            last = a.round + 1 >= ncut;
-            if (a.round > 0) {  // the top-k carried from the previous position
+            ci0 = min(a.pos, ncut);
+            ci1 = min(a.pos + 1, ncut);
+            last = a.pos + 1 >= ncut;
+            if (a.pos > 0) {  // the top-k carried from the previous position
                 top.hn = carry_in(a, top.s0, top.i0, qi);
                 __syncthreads();
             }
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(Sear
         }
         if constexpr (LIST) {
             carry_out(a, top.hs(), top.hid(), top.hn, qi, last, C, nnz_tot);
-            if (a.round == 0) {  // the cut lists, for the items of the later positions
+            if (a.pos == 0) {  // the cut lists, for the items of the later positions
                 if ((uint32_t)tid < ncut) a.ls_cut[(size_t)qi * a.cmax + tid] = L.cut[tid];
                 if (tid == 0) a.ls_ncut[qi] = ncut;
             }
@@ -887,7 +887,7 @@ hipError_t launch_search(const SearchArgs& a, uint32_t nt, uint32_t grid, size_t
     return hipGetLastError();
 }
 
-hipError_t launch_search_rounds(SearchArgs a, const ListSched& ls, uint32_t nt, uint32_t grid, size_t smem,
+hipError_t launch_search_positions(SearchArgs a, const ListSched& ls, uint32_t nt, uint32_t grid, size_t smem,
                                 hipStream_t stream) {
     if (a.nq == 0) return hipSuccess;
     const uint32_t cmax = a.cut, dim = a.ix.dim, qb = (a.nq + 255) / 256;
@@ -902,8 +902,8 @@ hipError_t launch_search_rounds(SearchArgs a, const ListSched& ls, uint32_t nt, 
     a.ls_hn = ls.hn;
     a.ls_cnt = ls.cnt;
     const uint32_t hn = cmax * (dim + 1);
-    auto round = [&](uint32_t r) {
-        a.round = r;
+    auto position = [&](uint32_t r) {
+        a.pos = r;
         a.queue = ls.queues + r;
         if (nt == 512)
             hipLaunchKernelGGL((k_search<512, true>), dim3(grid), dim3(512), smem, stream, a);
@@ -918,7 +918,7 @@ hipError_t launch_search_rounds(SearchArgs a, const ListSched& ls, uint32_t nt, 
     hipLaunchKernelGGL(k_items_scatter, dim3(qb), dim3(256), 0, stream, a.nq_dev, a.nq, cmax, dim, ls.cut, ls.ncut,
                        ls.term_rank, ls.key0, ls.hist, ls.items);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = round(0);
+    if (e == hipSuccess) e = position(0);
     if (e != hipSuccess || cmax < 2) return e;
     hipLaunchKernelGGL(k_items_count, dim3(qb), dim3(256), 0, stream, a.nq_dev, a.nq, cmax, dim, ls.cut, ls.ncut,
                        ls.term_rank, ls.hist);
@@ -926,7 +926,7 @@ hipError_t launch_search_rounds(SearchArgs a, const ListSched& ls, uint32_t nt, 
     hipLaunchKernelGGL(k_items_scatter, dim3(qb), dim3(256), 0, stream, a.nq_dev, a.nq, cmax, dim, ls.cut, ls.ncut,
                        ls.term_rank, (const uint32_t*)nullptr, ls.hist, ls.items);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    for (uint32_t r = 1; r < cmax && e == hipSuccess; ++r) e = round(r);
+    for (uint32_t r = 1; r < cmax && e == hipSuccess; ++r) e = position(r);
     return e;
 }
 

@@ -36,17 +36,18 @@ struct SearchArgs {
     uint32_t* list_term;    // [nq * prefix_stride] term of each cut list (0xFFFFFFFF past the cut), or NULL
     const double* probe_w;  // sanitized learned-probe parameters (fp64), or NULL for the heap_factor rule
     double tau;             // probe threshold: a probe-owned list evaluates the blocks with logit >= tau
-    // List-major schedule (mode == kModeList): round r processes the r-th cut
-    // list of every query that has one, the items of a round grouped by list
-    // (longest lists first); round 0 records every query's cut lists, and
-    // each query's top-k and counters are carried from round to round.
+    // List-major schedule (mode == kModeList): the launch for position r
+    // processes the r-th cut list of every query that has one, the items of
+    // a position grouped by list (longest lists first); position 0 records
+    // every query's cut lists, and each query's top-k and counters are
+    // carried from one position to the next.
     uint32_t mode;          // kModeQuery or kModeList
-    uint32_t round;         // kModeList: the cut position processed
-    uint32_t cmax;          // cut positions per query in ls_cut (= the query_cut, 1..kMaxRounds)
+    uint32_t pos;           // kModeList: the cut position processed
+    uint32_t cmax;          // cut positions per query in ls_cut (= the query_cut, 1..kMaxPositions)
     uint16_t* ls_cut;       // [nq * cmax] cut terms (written at position 0)
     uint32_t* ls_ncut;      // [nq] cut length (written at position 0)
-    const uint32_t* ls_items;  // query of every item, rounds one after another
-    const uint32_t* ls_seg;    // [cmax + 1] first item of each round
+    const uint32_t* ls_items;  // query of every item, positions one after another
+    const uint32_t* ls_seg;    // [cmax + 1] first item of each position
     float* ls_hs;           // [nq * k] carried top-k scores
     uint32_t* ls_hid;       // [nq * k] carried top-k ids
     uint32_t* ls_hn;        // [nq] carried top-k size
@@ -54,7 +55,7 @@ struct SearchArgs {
 };
 
 constexpr uint32_t kModeQuery = 0, kModeList = 1;
-constexpr uint32_t kMaxRounds = 64;  // largest query_cut served by the list-major schedule
+constexpr uint32_t kMaxPositions = 64;  // largest query_cut served by the list-major schedule
 
 // Device buffers of the list-major schedule for up to nq queries.
 struct ListSched {
@@ -64,7 +65,7 @@ struct ListSched {
     uint32_t* items = nullptr;
     uint32_t* key0 = nullptr;
     uint32_t* seg = nullptr;
-    uint32_t* queues = nullptr;  // [kMaxRounds + 1]
+    uint32_t* queues = nullptr;  // [kMaxPositions + 1]
     float* hs = nullptr;
     uint32_t* hid = nullptr;
     uint32_t* hn = nullptr;
@@ -75,9 +76,9 @@ struct ListSched {
 // nt = threads per workgroup (256 or 512); grid = number of persistent workgroups.
 size_t search_smem_bytes(uint32_t nt, uint32_t dim, uint32_t sort_cap, uint32_t k);
 hipError_t launch_search(const SearchArgs& a, uint32_t nt, uint32_t grid, size_t smem, hipStream_t stream);
-// The same search in the list-major schedule (a.cut in 1..kMaxRounds): item
+// The same search in the list-major schedule (a.cut in 1..kMaxPositions): item
 // construction and one launch per cut position.
-hipError_t launch_search_rounds(SearchArgs a, const ListSched& ls, uint32_t nt, uint32_t grid, size_t smem,
+hipError_t launch_search_positions(SearchArgs a, const ListSched& ls, uint32_t nt, uint32_t grid, size_t smem,
                                 hipStream_t stream);
 int search_blocks_per_cu(uint32_t nt, size_t smem);  // resident workgroups per CU (0 on error)
 
