@@ -239,11 +239,21 @@ void seismic_workspace_free(seismic_workspace* ws);
    position are grouped by list, longest lists first, so that queries
    visiting the same list run together and share its blocks in the caches;
    each query's top-k is carried between positions; used when 1 <=
-   query_cut <= 64, else query-major).  Results never depend on the shape.
+   query_cut <= 64, else query-major), 2 wide (for small batches: one
+   workgroup per (query, cut list) scores and sorts the list's summaries,
+   one workgroup per block evaluates the first `window` blocks (1..64) of
+   every sorted list, keeping each block's k best documents, then one
+   workgroup per query replays Algorithm 2's prune decisions in order over
+   those stored sets, gathering any later block itself; used when the batch
+   has at most 256 queries, 1 <= query_cut <= 32 and k <= 64, else
+   query-major).  Results never depend on the shape.
    Selecting schedule 1 (set_config, or the autotuner trying it) allocates
    the workspace's list-major buffers once: about max_queries * (450 + 8 *
-   max_k) bytes plus 256 bytes per index term.  EINVAL for unsupported
-   shapes, ENOMEM if those buffers do not fit. */
+   max_k) bytes plus 256 bytes per index term.  Schedule 2 allocates its
+   buffers once for c = min(max_queries, 256) queries: about c * 32 *
+   (6 * sort_cap + 64 * (20 + 8 * min(max_k, 64))) bytes, sort_cap being the
+   power of two at or above the index's longest list in blocks.  EINVAL for
+   unsupported shapes, ENOMEM if those buffers do not fit. */
 typedef struct {
     uint32_t threads;
     uint32_t blocks_per_cu;
@@ -251,9 +261,10 @@ typedef struct {
     uint32_t schedule;
 } seismic_launch_config;
 
-/* A new workspace uses 512 threads and window 16 for batches of up to 256
-   queries (one workgroup per query; lowest latency), 256 threads and
-   window 8 for larger ones.  set_config applies cfg to every batch-size
+/* A new workspace uses the wide schedule with 512 threads and window 32
+   for batches of up to 64 queries (lowest latency), the query-major
+   schedule with 512 threads and window 16 for up to 256 queries, and 256
+   threads and window 8 for larger ones.  set_config applies cfg to every batch-size
    bucket (<= 64, <= 256, <= 4096, larger); get_config returns the shape
    used for a batch of n_queries queries. */
 int seismic_workspace_set_config(seismic_workspace* ws, const seismic_launch_config* cfg);
@@ -269,7 +280,9 @@ typedef struct {
 /*
  * Autotuner for the persistent search kernel.  Times seismic_search_batch
  * on this batch under every launch shape that fits the device (threads
- * 256/512 x window 1/2/4/8/16 x resident workgroups per CU 1..max), one
+ * 256/512 x window 1/2/4/8/16 x resident workgroups per CU 1..max, for the
+ * query-major and, where they apply, list-major schedules; for the wide
+ * schedule, where it applies, threads 256/512 x window 8/16/32/64), one
  * warm-up and `reps` timed calls each (HIP events on `stream`; the call
  * waits for the stream), checks that every shape returns the same ids and
  * scores (EHIP-free mismatch => ESTATE), and stores the fastest shape for
@@ -420,7 +433,9 @@ typedef struct {
     uint32_t max_batch;          /* queries per batch */
     uint32_t n_slots;            /* batches in flight, 1..64 */
     uint32_t max_batch_nnz;      /* query nonzeros per batch, >= SEISMIC_MAX_QUERY_NNZ */
-    uint32_t use_graphs;         /* 1: each slot's search is a captured HIP graph (seismic_graph_create) */
+    uint32_t use_graphs;         /* 1: each slot's search is a captured HIP graph (seismic_graph_create),
+                                    plus graphs for batches of <= 256 and <= 64 queries in the
+                                    workspace's shapes for those sizes */
     seismic_launch_config launch; /* threads = 0: the workspace default */
 } seismic_server_params;
 

@@ -253,7 +253,7 @@ def seismic_workspace_free(ws):
 
 
 def seismic_workspace_set_config(ws, threads: int = 256, blocks_per_cu: int = 0, window: int = 4, schedule: int = 0):
-    """schedule: 0 query-major, 1 list-major (see seismic_launch_config)."""
+    """schedule: 0 query-major, 1 list-major, 2 wide (see seismic_launch_config)."""
     c = LaunchConfig(threads, blocks_per_cu, window, schedule)
     _check(load().seismic_workspace_set_config(ws, ctypes.byref(c)))
 

@@ -100,6 +100,8 @@ struct seismic_workspace {
     size_t q_rows_cap = 0, q_words_cap = 0;
     seismic_dev::ListSched ls;  // list-major schedule buffers (allocated on first request)
     std::vector<void*> ls_allocs;
+    seismic_dev::WideSched wd;  // wide schedule buffers (allocated on first request)
+    std::vector<void*> wd_allocs;
 };
 
 namespace {
@@ -108,9 +110,10 @@ int bucket_of(uint64_t nq) { return nq <= 64 ? 0 : nq <= 256 ? 1 : nq <= 4096 ? 
 
 int check_config(const seismic_workspace* ws, const seismic_launch_config* c) {
     if (c->threads != 256 && c->threads != 512) return fail(SEISMIC_EINVAL, "config: threads must be 256 or 512");
-    if (c->window < 1 || c->window > seismic_dev::kMaxW)
-        return fail(SEISMIC_EINVAL, "config: window must be in [1, %u]", seismic_dev::kMaxW);
-    if (c->schedule > 1) return fail(SEISMIC_EINVAL, "config: schedule must be 0 or 1");
+    if (c->schedule > 2) return fail(SEISMIC_EINVAL, "config: schedule must be 0, 1 or 2");
+    const uint32_t wmax = c->schedule == 2 ? seismic_dev::kWideMaxDepth : seismic_dev::kMaxW;
+    if (c->window < 1 || c->window > wmax)
+        return fail(SEISMIC_EINVAL, "config: window must be in [1, %u] for schedule %u", wmax, c->schedule);
     size_t smem = seismic_dev::search_smem_bytes(c->threads, ws->index->h.dim, ws->index->dev->sort_cap, ws->max_k);
     if (smem > ws->index->dev->smem_limit)
         return fail(SEISMIC_EINVAL, "config: %zu bytes of LDS needed, the device allows %zu", smem, ws->index->dev->smem_limit);
@@ -164,6 +167,47 @@ int ensure_list_sched(seismic_workspace* ws) {
     return SEISMIC_OK;
 }
 
+// Buffers of the wide schedule: up to kWideMaxBatch queries of the
+// workspace, kWideMaxCut cut lists, kWideMaxDepth speculated blocks per list,
+// top-k sets of min(max_k, kWideMaxK) entries.
+int ensure_wide_sched(seismic_workspace* ws) {
+    if (ws->wd.r) return SEISMIC_OK;
+    seismic_dev::WideSched w;
+    w.cap = std::max<uint32_t>(1, std::min(ws->max_queries, seismic_dev::kWideMaxBatch));
+    w.sort_cap = ws->index->dev->sort_cap;
+    w.k = std::min(ws->max_k, seismic_dev::kWideMaxK);
+    const size_t lists = (size_t)w.cap * seismic_dev::kWideMaxCut, blocks = lists * seismic_dev::kWideMaxDepth;
+    // evaluation items (chunks of kWideChunk documents) and their top-k
+    // sets: up to four per speculated block within 256 MB of sets; a list
+    // whose items do not fit speculates fewer blocks
+    w.icap = (uint32_t)std::max<size_t>(blocks, std::min<size_t>(4 * blocks, (size_t(256) << 20) / (8 * w.k)));
+    auto al = [&](auto*& p, size_t bytes) {
+        void* x = nullptr;
+        if (hipMalloc(&x, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
+        ws->wd_allocs.push_back(x);
+        p = (std::remove_reference_t<decltype(p)>)x;
+        return true;
+    };
+    bool ok = al(w.r, lists * w.sort_cap * 4) && al(w.ord, lists * w.sort_cap * 2) && al(w.nspec, lists * 4) &&
+              al(w.items, (size_t)w.icap * 16) && al(w.cnt, 16) && al(w.first, blocks * 4) &&
+              al(w.docs, blocks * 4) && al(w.nnz, blocks * 8) && al(w.ps, (size_t)w.icap * w.k * 4) &&
+              al(w.pid, (size_t)w.icap * w.k * 4);
+    if (!ok) {
+        for (void* x : ws->wd_allocs) (void)hipFree(x);
+        ws->wd_allocs.clear();
+        return fail(SEISMIC_ENOMEM, "workspace: wide schedule buffers do not fit");
+    }
+    ws->wd = w;
+    return SEISMIC_OK;
+}
+
+// Does the wide schedule serve this batch (buffers present, sizes within them)?
+bool wide_applies(const seismic_workspace* ws, uint64_t nq, const seismic_search_params* params, uint32_t nt) {
+    const size_t smem = seismic_dev::search_smem_bytes(nt, ws->index->h.dim, ws->index->dev->sort_cap, params->k);
+    return ws->wd.r && nq <= ws->wd.cap && params->query_cut >= 1 && params->query_cut <= seismic_dev::kWideMaxCut &&
+           params->k <= ws->wd.k && smem + seismic_dev::kWideMetaBytes <= ws->index->dev->smem_limit;
+}
+
 int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64_t* q_ptr, const uint32_t* q_words,
                  uint64_t nq, uint64_t nnz, const seismic_search_params* params, uint32_t* out_ids, float* out_scores,
                  const seismic_stats* stats, const seismic_launch_config& cfg, hipStream_t st,
@@ -201,7 +245,14 @@ int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64
     if (per_cu < 1) return fail(SEISMIC_EHIP, "search: kernel does not fit on a CU (%zu bytes of LDS)", smem);
     if (cfg.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)cfg.blocks_per_cu);
     uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ws->n_cu, nq);
-    if (cfg.schedule == 1 && ws->ls.cut && index->dev->term_rank && params->query_cut >= 1 &&
+    if (cfg.schedule == 2 && wide_applies(ws, nq, params, nt)) {
+        a.depth = cfg.window;
+        const size_t smem_eval = seismic_dev::search_smem_bytes(256, index->h.dim, index->dev->sort_cap, params->k);
+        const int per_cu_eval = seismic_dev::search_blocks_per_cu(256, smem_eval);
+        if (per_cu_eval < 1) return fail(SEISMIC_EHIP, "search: kernel does not fit on a CU (%zu bytes of LDS)", smem_eval);
+        HIP_TRY(seismic_dev::launch_search_wide(a, ws->wd, nt, (uint32_t)per_cu * (uint32_t)ws->n_cu, smem,
+                                                (uint32_t)per_cu_eval * (uint32_t)ws->n_cu, smem_eval, st));
+    } else if (cfg.schedule == 1 && ws->ls.cut && index->dev->term_rank && params->query_cut >= 1 &&
         params->query_cut <= seismic_dev::kMaxPositions) {
         seismic_dev::ListSched ls = ws->ls;
         ls.term_rank = index->dev->term_rank;
@@ -393,15 +444,22 @@ int seismic_workspace_create(const seismic_index* index, uint32_t max_queries, u
     ws->device = index->dev->device;
     ws->max_queries = max_queries;
     ws->max_k = max_k;
-    // default shapes: a batch of up to 256 queries runs one query per CU with
-    // 512-thread workgroups (lower latency when the chip is not full: 1.8 ms
-    // against 2.9 ms for one query at 8.8M), larger batches 256-thread
-    // workgroups, three per CU; the autotuner can replace any of them
-    for (int b = 0; b < kBuckets; ++b) ws->cfg[b] = seismic_launch_config{b < 2 ? 512u : 256u, 0, b < 2 ? 16u : 8u, 0};
+    // default shapes: a batch of up to 64 queries runs the wide schedule
+    // (512-thread list pass and traversal, 32 speculated blocks per list: at
+    // 8.8M, 0.29 ms for one query and 1.0 ms for 32, against 1.7 and 2.1 ms
+    // query-major), up to 256 queries one query per CU with 512-thread
+    // workgroups, larger batches 256-thread workgroups, three per CU; the
+    // autotuner can replace any of them
+    ws->cfg[0] = seismic_launch_config{512u, 0, 32u, 2u};
+    ws->cfg[1] = seismic_launch_config{512u, 0, 16u, 0};
+    for (int b = 2; b < kBuckets; ++b) ws->cfg[b] = seismic_launch_config{256u, 0, 8u, 0};
     int rc = check_config(ws, &ws->cfg[2]);
     if (rc) { delete ws; return rc; }
-    for (int b = 0; b < 2; ++b)
-        if (check_config(ws, &ws->cfg[b]) != SEISMIC_OK) ws->cfg[b] = ws->cfg[2];  // 512 threads do not fit
+    if (check_config(ws, &ws->cfg[1]) != SEISMIC_OK) ws->cfg[1] = ws->cfg[2];  // 512 threads do not fit
+    if (check_config(ws, &ws->cfg[0]) != SEISMIC_OK) {
+        ws->cfg[0].threads = 256;
+        if (check_config(ws, &ws->cfg[0]) != SEISMIC_OK) ws->cfg[0] = ws->cfg[2];
+    }
     clear_error();
     DeviceGuard g(ws->device);
     hipDeviceProp_t prop;
@@ -428,15 +486,17 @@ void seismic_workspace_free(seismic_workspace* ws) {
     (void)hipFree(ws->q_ptr);
     (void)hipFree(ws->q_words);
     for (void* x : ws->ls_allocs) (void)hipFree(x);
+    for (void* x : ws->wd_allocs) (void)hipFree(x);
     delete ws;
 }
 
 int seismic_workspace_set_config(seismic_workspace* ws, const seismic_launch_config* cfg) {
     if (!ws || !cfg) return fail(SEISMIC_EINVAL, "config: null argument");
     int rc = check_config(ws, cfg);
-    if (!rc && cfg->schedule == 1) {
+    if (!rc && cfg->schedule >= 1) {
         DeviceGuard g(ws->device);
-        rc = g.ok() ? ensure_list_sched(ws) : fail(SEISMIC_EHIP, "config: cannot select device");
+        rc = !g.ok() ? fail(SEISMIC_EHIP, "config: cannot select device")
+                     : cfg->schedule == 1 ? ensure_list_sched(ws) : ensure_wide_sched(ws);
     }
     if (rc) return rc;
     for (auto& c : ws->cfg) c = *cfg;
@@ -474,8 +534,16 @@ int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, cons
         q_ptr = ws->q_ptr;
         q_words = ws->q_words;
     }
+    const seismic_launch_config& cfg = ws->cfg[bucket_of(queries->n_rows)];
+    if (cfg.schedule == 2 && !ws->wd.r) {
+        // allocate the wide schedule's buffers unless the stream is being
+        // captured (the batch then runs query-major)
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) (void)ensure_wide_sched(ws);
+        clear_error();
+    }
     return launch_batch(index, ws, q_ptr, q_words, queries->n_rows, queries->nnz, params, out_ids, out_scores, stats,
-                        ws->cfg[bucket_of(queries->n_rows)], st);
+                        cfg, st);
 }
 
 int seismic_autotune(const seismic_index* index, seismic_workspace* ws, const seismic_csr* queries,
@@ -506,13 +574,23 @@ int seismic_autotune(const seismic_index* index, seismic_workspace* ws, const se
     // the list-major schedule is tried when it applies and its buffers fit
     const bool lists = params->query_cut >= 1 && params->query_cut <= seismic_dev::kMaxPositions &&
                        index->dev->term_rank && ensure_list_sched(ws) == SEISMIC_OK;
-    for (uint32_t sched = 0; sched <= (lists ? 1u : 0u) && !err; ++sched)
+    // the wide schedule for small batches (speculation depths 8..64, full grid)
+    const bool wide = queries->n_rows <= seismic_dev::kWideMaxBatch && ensure_wide_sched(ws) == SEISMIC_OK &&
+                      wide_applies(ws, queries->n_rows, params, 256);
+    clear_error();
+    for (uint32_t sched = 0; sched <= 2 && !err; ++sched)
     for (uint32_t nt : {256u, 512u}) {
+        if ((sched == 1 && !lists) || (sched == 2 && !wide)) break;
         size_t smem = seismic_dev::search_smem_bytes(nt, index->h.dim, index->dev->sort_cap, params->k);
         if (smem > index->dev->smem_limit) continue;
+        if (sched == 2 && !wide_applies(ws, queries->n_rows, params, nt)) continue;
         const int max_pc = seismic_dev::search_blocks_per_cu(nt, smem);
-        for (int pc = 1; pc <= max_pc && !err; ++pc) {
-            for (uint32_t w : {1u, 2u, 4u, 8u, 16u}) {
+        for (int pc = sched == 2 ? max_pc : 1; pc <= max_pc && !err; ++pc) {
+            static const uint32_t kWindows[5] = {1, 2, 4, 8, 16}, kDepths[4] = {8, 16, 32, 64};
+            const uint32_t* wl = sched == 2 ? kDepths : kWindows;
+            const int n_wl = sched == 2 ? 4 : 5;
+            for (int wi = 0; wi < n_wl; ++wi) {
+                const uint32_t w = wl[wi];
                 seismic_launch_config c{nt, (uint32_t)pc, w, sched};
                 // warm-up run, then compare its results with the first shape's
                 err = launch_batch(index, ws, queries->row_ptr, queries->words, queries->n_rows, queries->nnz, params,
@@ -572,6 +650,8 @@ int seismic_graph_create(const seismic_index* index, seismic_workspace* ws, cons
     seismic_batch_graph* gr = new (std::nothrow) seismic_batch_graph();
     if (!gr) return fail(SEISMIC_ENOMEM, "graph: host allocation failed");
     gr->device = ws->device;
+    if (ws->cfg[bucket_of(queries->n_rows)].schedule == 2) (void)ensure_wide_sched(ws);  // before capture
+    clear_error();
     hipStream_t cs = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);

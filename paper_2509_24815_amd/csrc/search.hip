@@ -67,6 +67,11 @@ struct SearchLds {
     uint32_t* clen;    // [NT] row lengths
     double* cacc;      // [NT]
     uint8_t* cslot;    // [NT]
+    // wide schedule traversal only (carved past the common layout): the
+    // speculated blocks of the current list by sorted position
+    uint32_t* wfirst;  // [kWideMaxDepth] first evaluation item
+    uint32_t* wdocs;   // [kWideMaxDepth] documents
+    uint64_t* wnnz;    // [kWideMaxDepth] nonzeros
 };
 
 __host__ __device__ inline uint32_t r16u(uint64_t x) { return (uint32_t)((x + 15) & ~uint64_t(15)); }
@@ -87,9 +92,10 @@ __host__ __device__ inline size_t union_bytes(uint32_t P) {
     return m > gath ? m : gath;
 }
 
+// Returns the end of the layout (search_smem_bytes past base).
 template <int NT>
-__device__ inline void carve_lds(uint8_t* base, uint32_t dim, uint32_t P, uint32_t k, SearchLds<NT>& L,
-                                 TopK<NT>& top) {
+__device__ inline uint8_t* carve_lds(uint8_t* base, uint32_t dim, uint32_t P, uint32_t k, SearchLds<NT>& L,
+                                     TopK<NT>& top) {
     const uint32_t nw = (dim + 63) / 64;
     uint8_t* p = base;
     L.region_bytes = region_bytes_for(dim);
@@ -133,6 +139,7 @@ __device__ inline void carve_lds(uint8_t* base, uint32_t dim, uint32_t P, uint32
     L.cdoc = (uint32_t*)carve(q, 4ull * NT);
     L.clen = (uint32_t*)carve(q, 4ull * NT);
     L.cslot = (uint8_t*)carve(q, 1ull * NT);
+    return u + union_bytes<NT>(P);
 }
 
 template <int NT>
@@ -365,6 +372,60 @@ __device__ inline uint32_t fold_window_pending(const SearchLds<NT>& L, TopK<NT>&
     return nc ? top.merge_pending(nc) : 0u;
 }
 
+// Step 2a for the nb blocks of a list (first block b0, summary entries
+// [S0, S1)): per block, sum(q) in L.A and sum(q * code) in L.B.  Every
+// thread calls it; it ends with a barrier.
+template <int NT, typename Look>
+__device__ __forceinline__ void summary_sums(const DevIdx& ix, const SearchLds<NT>& L, const Look& look, uint32_t b0,
+                                             uint32_t nb, uint64_t S0, uint64_t S1) {
+    const int tid = threadIdx.x;
+    for (uint32_t i = tid; i <= nb; i += NT) L.soff[i] = (uint32_t)(ix.blk_sum_off[b0 + i] - S0);
+    for (uint32_t i = tid; i < nb; i += NT) { L.A[i] = 0.0; L.B[i] = 0.0; }
+    __syncthreads();
+    const uint64_t gend = (S1 + 7) >> 3;
+    for (uint64_t g0 = (S0 >> 3) + tid; g0 < gend; g0 += (uint64_t)NT * kSumUnroll) {
+        uint4 tv[kSumUnroll];
+        uint2 cv[kSumUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kSumUnroll; ++u) {
+            const uint64_t g = g0 + (uint64_t)u * NT;
+            if (g < gend) {
+                tv[u] = *(const uint4*)(ix.sum_term + (g << 3));
+                cv[u] = *(const uint2*)(ix.sum_code + (g << 3));
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kSumUnroll; ++u) {
+            const uint64_t g = g0 + (uint64_t)u * NT;
+            if (g < gend) summary_group<NT, Look>(L, look, g << 3, tv[u], cv[u], S0, S1, nb);
+        }
+    }
+    __syncthreads();
+}
+
+// Bitonic sort of (L.r, L.ord)[0, Pl) into (r desc, ord asc) order; Pl is a
+// power of two.  Every thread calls it; it ends with a barrier when Pl > 1.
+template <int NT>
+__device__ __forceinline__ void sort_blocks(const SearchLds<NT>& L, uint32_t Pl) {
+    const int tid = threadIdx.x;
+    for (uint32_t kk = 2; kk <= Pl; kk <<= 1) {
+        for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (uint32_t i = tid; i < Pl; i += NT) {
+                const uint32_t l = i ^ jj;
+                if (l > i) {
+                    const float ri = L.r[i], rl = L.r[l];
+                    const uint32_t oi = L.ord[i], ol = L.ord[l];
+                    const bool l_first = rl > ri || (rl == ri && ol < oi);
+                    if (((i & kk) == 0) ? l_first : !l_first) {
+                        L.r[i] = rl; L.r[l] = ri; L.ord[i] = (uint16_t)ol; L.ord[l] = (uint16_t)oi;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 struct Counters {
     uint64_t sum = 0, blocks = 0, eval = 0, docs = 0, tests = 0, nnz = 0;
 };
@@ -399,8 +460,10 @@ __device__ __forceinline__ void carry_out(const SearchArgs& a, const float* H, c
     }
 }
 
-// Steps 2a-2c for the cut lists ci0 .. ci1 - 1 of query qi.
-template <int NT, typename Look>
+// Steps 2a-2c for the cut lists ci0 .. ci1 - 1 of query qi.  WIDE: the
+// wide schedule's traversal (sorted summary scores and the speculated
+// blocks' top-k sets come from the list and evaluation passes).
+template <int NT, typename Look, bool WIDE>
 __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<NT>& L, TopK<NT>& top, const Look& look, uint32_t qi,
                           uint32_t ci0, uint32_t ci1, uint32_t nvalid, Counters& C) {
     const int tid = threadIdx.x;
@@ -422,29 +485,22 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
         const uint64_t S0 = ix.blk_sum_off[b0], S1 = ix.blk_sum_off[b1];
         C.sum += S1 - S0;
         C.blocks += nb;
-        for (uint32_t i = tid; i <= nb; i += NT) L.soff[i] = (uint32_t)(ix.blk_sum_off[b0 + i] - S0);
-        for (uint32_t i = tid; i < nb; i += NT) { L.A[i] = 0.0; L.B[i] = 0.0; }
-        __syncthreads();
-        const uint64_t gend = (S1 + 7) >> 3;
-        for (uint64_t g0 = (S0 >> 3) + tid; g0 < gend; g0 += (uint64_t)NT * kSumUnroll) {
-            uint4 tv[kSumUnroll];
-            uint2 cv[kSumUnroll];
-#pragma unroll
-            for (uint32_t u = 0; u < kSumUnroll; ++u) {
-                const uint64_t g = g0 + (uint64_t)u * NT;
-                if (g < gend) {
-                    tv[u] = *(const uint4*)(ix.sum_term + (g << 3));
-                    cv[u] = *(const uint2*)(ix.sum_code + (g << 3));
-                }
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < kSumUnroll; ++u) {
-                const uint64_t g = g0 + (uint64_t)u * NT;
-                if (g < gend) summary_group<NT, Look>(L, look, g << 3, tv[u], cv[u], S0, S1, nb);
-            }
+        [[maybe_unused]] const float* wr = nullptr;     // WIDE: sorted scores of this list
+        [[maybe_unused]] const uint16_t* wo = nullptr;  // WIDE: their block indexes
+        [[maybe_unused]] uint32_t D = 0;                // WIDE: speculated blocks (sorted positions [0, D))
+        [[maybe_unused]] size_t wslot = 0;              // WIDE: result slot of sorted position 0
+        if constexpr (WIDE) {
+            const size_t lb = ((size_t)qi * a.cmax + ci) * a.sort_cap;
+            wr = a.wd_r + lb;
+            wo = a.wd_ord + lb;
+            D = a.wd_nspec[(size_t)qi * a.cmax + ci];
+            wslot = ((size_t)qi * a.cmax + ci) * a.depth;
+        } else {
+            summary_sums<NT, Look>(ix, L, look, b0, nb, S0, S1);
         }
-        __syncthreads();
         // ---------------------------------------- b. prefilter + sort
+        // (WIDE: the scores arrive sorted, so the survivors of the
+        // heap_factor rule are a prefix; L.ord holds sorted positions)
         const bool full0 = top.full();
         const double hmin0 = full0 ? (double)top.min_score() : 0.0;
         const bool learned = full0 && a.probe_w != nullptr;
@@ -454,9 +510,20 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
             float rv = 0.0f;
             bool keep = false;
             if (i < nb) {
-                rv = (float)((double)ix.blk_m[b0 + i] * L.A[i] + (double)ix.blk_delta[b0 + i] * L.B[i]);
+                uint32_t bi = i;
+                if constexpr (WIDE) {
+                    rv = wr[i];
+                    bi = wo[i];
+                    if (i < D) {
+                        L.wfirst[i] = a.wd_first[wslot + i];
+                        L.wdocs[i] = a.wd_docs[wslot + i];
+                        L.wnnz[i] = a.wd_nnz[wslot + i];
+                    }
+                } else {
+                    rv = (float)((double)ix.blk_m[b0 + i] * L.A[i] + (double)ix.blk_delta[b0 + i] * L.B[i]);
+                }
                 if (learned) {
-                    keep = probe_keeps(a.probe_w, a.tau, rv, hmin0, ix.blk_post_off[b0 + i + 1] - ix.blk_post_off[b0 + i],
+                    keep = probe_keeps(a.probe_w, a.tau, rv, hmin0, ix.blk_post_off[b0 + bi + 1] - ix.blk_post_off[b0 + bi],
                                        nvalid, ci);
                 } else {
                     keep = !(full0 && (double)rv * (double)a.hf < hmin0);
@@ -471,36 +538,58 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
         while (Pl < nsurv) Pl <<= 1;
         for (uint32_t i = nsurv + tid; i < Pl; i += NT) { L.r[i] = -INFINITY; L.ord[i] = 0xFFFFu; }
         __syncthreads();
-        if (nsurv > 1 && !learned) {
-            for (uint32_t kk = 2; kk <= Pl; kk <<= 1) {
-                for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
-                    for (uint32_t i = tid; i < Pl; i += NT) {
-                        const uint32_t l = i ^ jj;
-                        if (l > i) {
-                            const float ri = L.r[i], rl = L.r[l];
-                            const uint32_t oi = L.ord[i], ol = L.ord[l];
-                            const bool l_first = rl > ri || (rl == ri && ol < oi);
-                            if (((i & kk) == 0) ? l_first : !l_first) {
-                                L.r[i] = rl; L.r[l] = ri; L.ord[i] = (uint16_t)ol; L.ord[l] = (uint16_t)oi;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-        }
+        if (!WIDE && nsurv > 1 && !learned) sort_blocks<NT>(L, Pl);
         // ---------------------------------------- c. traversal
         uint32_t pos = 0, evaluated = 0;
         bool stop = false;
         while (pos < nsurv && !stop) {
+            uint32_t nwb = 0, tot = 0;
+            [[maybe_unused]] bool spec = false;   // WIDE: a window of speculated blocks
+            [[maybe_unused]] uint32_t wdocs = 0;  // WIDE: documents of the window's blocks
+            [[maybe_unused]] uint64_t wnnz = 0;   // WIDE: their nonzeros (speculated blocks)
+            if constexpr (WIDE) spec = L.ord[pos] < D;
+            if (spec) {
+                // consecutive speculated blocks; their chunks' stored top-k
+                // sets are the candidates, which yields the same top-k as all
+                // of their documents (a document outside its chunk's k best
+                // has k better ones in the same block)
+                const uint32_t k = a.k;
+                // blocks while their candidates fit (a speculated block alone always does)
+                while (nwb < kMaxW && pos + nwb < nsurv && L.ord[pos + nwb] < D) {
+                    const uint32_t c = (L.wdocs[L.ord[pos + nwb]] + kWideChunk - 1) / kWideChunk * k;
+                    if (nwb > 0 && tot + c > (uint32_t)NT) break;
+                    tot += c;
+                    ++nwb;
+                }
+                if ((uint32_t)tid < tot) {
+                    uint32_t s = 0, run = 0;
+                    for (;; ++s) {
+                        const uint32_t c = (L.wdocs[L.ord[pos + s]] + kWideChunk - 1) / kWideChunk * k;
+                        if ((uint32_t)tid < run + c) break;
+                        run += c;
+                    }
+                    const size_t e = (size_t)L.wfirst[L.ord[pos + s]] * k + ((uint32_t)tid - run);
+                    L.cacc[tid] = (double)a.wd_ps[e];
+                    L.cdoc[tid] = a.wd_pid[e];
+                    L.clen[tid] = 0;
+                    L.cslot[tid] = (uint8_t)s;
+                }
+                if ((uint32_t)tid < nwb) {
+                    L.wlen[tid] = L.wdocs[L.ord[pos + tid]];
+                    L.crs[tid] = L.wnnz[L.ord[pos + tid]];
+                }
+                __syncthreads();
+                for (uint32_t s = 0; s < nwb; ++s) { wdocs += L.wlen[s]; wnnz += L.crs[s]; }
+            } else {
             if ((uint32_t)tid < W && pos + tid < nsurv) {
-                const uint32_t b = b0 + L.ord[pos + tid];
+                uint32_t b;
+                if constexpr (WIDE) b = b0 + wo[L.ord[pos + tid]];
+                else b = b0 + L.ord[pos + tid];
                 const uint32_t p0 = ix.blk_post_off[b];
                 L.wp0[tid] = p0;
                 L.wlen[tid] = ix.blk_post_off[b + 1] - p0;
             }
             __syncthreads();
-            uint32_t nwb = 0, tot = 0;
             for (uint32_t s = 0; s < W && pos + s < nsurv; ++s) {
                 const uint32_t len = L.wlen[s];
                 if (s > 0 && tot + len > (uint32_t)NT) break;
@@ -533,6 +622,8 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
             }
             __syncthreads();
             gather_and_score<NT, Look>(ix, L, look, tot, nwb, 0);
+            wdocs = tot;
+            }
             // Whole-window fold.  A probe-owned list makes no decisions.  With
             // the heap_factor rule and a heap already full, fold everything
             // into the idle buffer: heap.min only grows while the window is
@@ -543,7 +634,12 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
             bool folded = false;
             if (learned) {
                 evaluated += nwb;
-                C.docs += tot;
+                if constexpr (WIDE) {
+                    C.docs += wdocs;
+                    if (tid == 0) C.nnz += wnnz;
+                } else {
+                    C.docs += tot;
+                }
                 fold_slot<NT>(L, top, tot, -1, C.nnz);
                 folded = true;
             } else if (nwb > 1 && top.full() && (double)L.r[pos] * (double)a.hf >= (double)top.min_score()) {
@@ -554,8 +650,13 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
                     top.commit(ns);
                     evaluated += nwb;
                     C.tests += nwb;
-                    C.docs += tot;
                     C.nnz += nnz;
+                    if constexpr (WIDE) {
+                        C.docs += wdocs;
+                        if (tid == 0) C.nnz += wnnz;
+                    } else {
+                        C.docs += tot;
+                    }
                     folded = true;
                 }
             }
@@ -566,6 +667,8 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
                 }
                 ++evaluated;
                 C.docs += L.wlen[s];
+                if constexpr (WIDE)
+                    if (spec && tid == 0) C.nnz += L.crs[s];
                 fold_slot<NT>(L, top, tot, (int)s, C.nnz);
             }
             pos += stop ? 0u : nwb;
@@ -580,94 +683,76 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
     }
 }
 
-// LIST: the list-major schedule's per-position kernel (a separate instance, so that
-// the query-major kernel carries none of its code; its carry code would
-// take it past three workgroups per CU, so the bound keeps three and the
-// compiler spills a few values of that code).
-template <int NT, bool LIST>
-__global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(SearchArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
+// Step 1 for query qi: validation flags, the term lookup in LDS (u8 slot
+// table, or bitmap + prefix counts + values for long queries) and, with CUT,
+// the cut lists in L.cut.  Every thread calls it; it ends with a barrier.
+struct Ingested {
+    uint64_t q0;      // first word of the query's row
+    uint32_t nqe;     // words read (at most kMaxQ)
+    uint32_t nvalid;  // valid distinct terms
+    uint32_t ncut;    // cut lists (CUT only, else 0)
+    uint32_t status;  // SEISMIC_QSTATUS_* bits
+    bool u8mode;      // slot table (else bitmap)
+};
+
+template <int NT, bool CUT>
+__device__ __forceinline__ Ingested ingest_query(const SearchArgs& a, const SearchLds<NT>& L, uint32_t qi, uint32_t nw) {
     const int tid = threadIdx.x;
     const DevIdx& ix = a.ix;
-    const uint32_t nw = (ix.dim + 63u) / 64u;
-    SearchLds<NT> L;
-    TopK<NT> top;
-    carve_lds<NT>(smem, ix.dim, a.sort_cap, a.k, L, top);
-    for (uint32_t i = tid; i < L.region_bytes / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
-    if (tid == 0) L.qv[0] = 0.0;
+    const uint64_t q1 = min(a.q_ptr[qi + 1], a.q_nnz), q0 = min(a.q_ptr[qi], q1);
+    const uint64_t raw = q1 - q0;
+    const uint32_t nqe = (uint32_t)min<uint64_t>(raw, (uint64_t)kMaxQ);
+    if (tid < 12) L.misc[tid] = 0;  // 8..9: query mass (fp64), 10: alpha_q-MSS size
     __syncthreads();
-
-    const uint32_t nq = a.nq_dev ? min(*a.nq_dev, a.nq) : a.nq;
-    // work items: queries, or at a list-major position the queries holding a
-    // cut list at this position
-    uint32_t it0 = 0, n_items = nq;
-    if constexpr (LIST) {
-        it0 = a.ls_seg[a.pos];
-        n_items = a.ls_seg[a.pos + 1] - it0;
+    uint32_t st = (raw > (uint64_t)kMaxQ) ? 4u : 0u;
+    for (uint32_t j = tid; j < nqe; j += NT) {
+        const uint32_t w = a.q_words[q0 + j];
+        const uint32_t t = w & 0xFFFFu, h = w >> 16;
+        bool keep = true;
+        if (t >= ix.dim) { st |= 1u; keep = false; }
+        if (!half_ok(h)) { st |= 8u; keep = false; }
+        if (j > 0 && t <= (a.q_words[q0 + j - 1] & 0xFFFFu)) st |= 2u;
+        if (keep) {
+            const uint64_t bit = 1ull << (t & 63u);
+            const uint64_t old = atomicOr((unsigned long long*)&L.bq.bits[t >> 6], (unsigned long long)bit);
+            if (old & bit) { st |= 2u; keep = false; }  // repeated term: first writer wins
+        }
+        L.q_term[j] = keep ? (uint16_t)t : (uint16_t)0xFFFFu;
+        L.q_half[j] = (uint16_t)h;
     }
-    for (;;) {
-        // ------------------------------------------------ next query
-        if (tid == 0) L.misc[15] = atomicAdd(a.queue, 1u);
-        __syncthreads();
-        const uint32_t item = __builtin_amdgcn_readfirstlane(L.misc[15]);
-        if (item >= n_items) break;
-        const uint32_t qi = __builtin_amdgcn_readfirstlane(LIST ? a.ls_items[it0 + item] : item);
-        top.which = 0;
-        top.hn = 0;
-
-        // ---------------------------------------------------------- ingest
-        const uint64_t q1 = min(a.q_ptr[qi + 1], a.q_nnz), q0 = min(a.q_ptr[qi], q1);
-        const uint64_t raw = q1 - q0;
-        const uint32_t nqe = (uint32_t)min<uint64_t>(raw, (uint64_t)kMaxQ);
-        if (tid < 12) L.misc[tid] = 0;  // 8..9: query mass (fp64), 10: alpha_q-MSS size
-        __syncthreads();
-        uint32_t st = (raw > (uint64_t)kMaxQ) ? 4u : 0u;
-        for (uint32_t j = tid; j < nqe; j += NT) {
-            const uint32_t w = a.q_words[q0 + j];
-            const uint32_t t = w & 0xFFFFu, h = w >> 16;
-            bool keep = true;
-            if (t >= ix.dim) { st |= 1u; keep = false; }
-            if (!half_ok(h)) { st |= 8u; keep = false; }
-            if (j > 0 && t <= (a.q_words[q0 + j - 1] & 0xFFFFu)) st |= 2u;
-            if (keep) {
-                const uint64_t bit = 1ull << (t & 63u);
-                const uint64_t old = atomicOr((unsigned long long*)&L.bq.bits[t >> 6], (unsigned long long)bit);
-                if (old & bit) { st |= 2u; keep = false; }  // repeated term: first writer wins
-            }
-            L.q_term[j] = keep ? (uint16_t)t : (uint16_t)0xFFFFu;
-            L.q_half[j] = (uint16_t)h;
-        }
-        if (st) atomicOr(&L.misc[0], st);
-        __syncthreads();
-        build_prefix<NT>(L.bq.bits, L.bq.pref, nw, L.scratch);
-        uint32_t nvalid_local = 0;
-        double mass_local = 0.0;
-        for (uint32_t j = tid; j < nqe; j += NT) {
-            const bool v = L.q_term[j] != 0xFFFFu;
-            nvalid_local += v ? 1u : 0u;
-            if (v) mass_local += (double)half_bits_to_float(L.q_half[j]);
-        }
-        if (nvalid_local) atomicAdd(&L.misc[1], nvalid_local);
-        if (a.qmass > 0.0 && mass_local != 0.0) atomicAdd((double*)&L.misc[8], mass_local);
-        __syncthreads();
-        const uint32_t nvalid = __builtin_amdgcn_readfirstlane(L.misc[1]);
-        const bool u8mode = nvalid <= kMaxSlots;
-        const uint32_t ncut0 = (a.cut == 0 || a.cut > nvalid) ? nvalid : a.cut;
-        const double mass_target = a.qmass * *(const double*)&L.misc[8];
-        // slot of every valid entry (1-based rank of its term)
-        uint32_t my_slot[kMaxQ / NT];
+    if (st) atomicOr(&L.misc[0], st);
+    __syncthreads();
+    build_prefix<NT>(L.bq.bits, L.bq.pref, nw, L.scratch);
+    uint32_t nvalid_local = 0;
+    double mass_local = 0.0;
+    for (uint32_t j = tid; j < nqe; j += NT) {
+        const bool v = L.q_term[j] != 0xFFFFu;
+        nvalid_local += v ? 1u : 0u;
+        if (v) mass_local += (double)half_bits_to_float(L.q_half[j]);
+    }
+    if (nvalid_local) atomicAdd(&L.misc[1], nvalid_local);
+    if (a.qmass > 0.0 && mass_local != 0.0) atomicAdd((double*)&L.misc[8], mass_local);
+    __syncthreads();
+    const uint32_t nvalid = __builtin_amdgcn_readfirstlane(L.misc[1]);
+    const bool u8mode = nvalid <= kMaxSlots;
+    const uint32_t ncut0 = (a.cut == 0 || a.cut > nvalid) ? nvalid : a.cut;
+    const double mass_target = a.qmass * *(const double*)&L.misc[8];
+    (void)mass_target;
+    // slot of every valid entry (1-based rank of its term)
+    uint32_t my_slot[kMaxQ / NT];
 #pragma unroll
-        for (uint32_t r = 0; r < kMaxQ / NT; ++r) {
-            const uint32_t j = tid + r * NT;
-            my_slot[r] = 0;
-            if (j >= nqe) continue;
-            const uint32_t t = L.q_term[j];
-            if (t == 0xFFFFu) continue;
-            const uint64_t w = L.bq.bits[t >> 6];
-            const uint32_t slot = L.bq.pref[t >> 6] + (uint32_t)__popcll(w & ((1ull << (t & 63u)) - 1ull));
-            my_slot[r] = slot + 1;
-            if (u8mode) L.qv[slot + 1] = (double)half_bits_to_float(L.q_half[j]);
-        }
+    for (uint32_t r = 0; r < kMaxQ / NT; ++r) {
+        const uint32_t j = tid + r * NT;
+        my_slot[r] = 0;
+        if (j >= nqe) continue;
+        const uint32_t t = L.q_term[j];
+        if (t == 0xFFFFu) continue;
+        const uint64_t w = L.bq.bits[t >> 6];
+        const uint32_t slot = L.bq.pref[t >> 6] + (uint32_t)__popcll(w & ((1ull << (t & 63u)) - 1ull));
+        my_slot[r] = slot + 1;
+        if (u8mode) L.qv[slot + 1] = (double)half_bits_to_float(L.q_half[j]);
+    }
+    if constexpr (CUT) {
         // cut order: value desc (positive fp16: bit order), then term asc.
         // With alpha_q > 0 the cut also stops at the alpha_q-MSS of the query:
         // an entry belongs to it while the mass ranked before it is below
@@ -690,22 +775,84 @@ __global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(Sear
             if (a.qmass > 0.0 && before < mass_target) ++in_mss;
         }
         if (in_mss) atomicAdd(&L.misc[10], in_mss);
-        const uint32_t status = __builtin_amdgcn_readfirstlane(L.misc[0]);
+    }
+    const uint32_t status = __builtin_amdgcn_readfirstlane(L.misc[0]);
+    __syncthreads();
+    const uint32_t ncut = CUT ? __builtin_amdgcn_readfirstlane(a.qmass > 0.0 ? min(ncut0, L.misc[10]) : ncut0) : 0u;
+    if (u8mode) {
+        // bitmap + prefix -> slot table
+        for (uint32_t i = tid; i < (10 * nw + 15) / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
         __syncthreads();
-        const uint32_t ncut = __builtin_amdgcn_readfirstlane(a.qmass > 0.0 ? min(ncut0, L.misc[10]) : ncut0);
-        if (u8mode) {
-            // bitmap + prefix -> slot table
-            for (uint32_t i = tid; i < (10 * nw + 15) / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
-            __syncthreads();
 #pragma unroll
-            for (uint32_t r = 0; r < kMaxQ / NT; ++r)
-                if (my_slot[r]) L.region[L.q_term[tid + r * NT]] = (uint8_t)my_slot[r];
-        } else {
+        for (uint32_t r = 0; r < kMaxQ / NT; ++r)
+            if (my_slot[r]) L.region[L.q_term[tid + r * NT]] = (uint8_t)my_slot[r];
+    } else {
 #pragma unroll
-            for (uint32_t r = 0; r < kMaxQ / NT; ++r)
-                if (my_slot[r]) L.bq.val[my_slot[r] - 1] = half_bits_to_float(L.q_half[tid + r * NT]);
+        for (uint32_t r = 0; r < kMaxQ / NT; ++r)
+            if (my_slot[r]) L.bq.val[my_slot[r] - 1] = half_bits_to_float(L.q_half[tid + r * NT]);
+    }
+    __syncthreads();
+    return Ingested{q0, nqe, nvalid, ncut, status, u8mode};
+}
+
+// Puts the lookup region of an ingested query back to all-zero.
+template <int NT>
+__device__ __forceinline__ void restore_region(const SearchArgs& a, const SearchLds<NT>& L, const Ingested& in) {
+    const int tid = threadIdx.x;
+    if (in.u8mode) {
+        for (uint32_t j = tid; j < in.nqe; j += NT) {
+            const uint32_t t = a.q_words[in.q0 + j] & 0xFFFFu;
+            if (t < a.ix.dim) L.region[t] = 0;
         }
+    } else {
+        for (uint32_t i = tid; i < L.region_bytes / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+}
+
+// LIST: the list-major schedule's per-position kernel (a separate instance, so that
+// the query-major kernel carries none of its code; its carry code would
+// take it past three workgroups per CU, so the bound keeps three and the
+// compiler spills a few values of that code).
+template <int NT, bool LIST, bool WIDE = false>
+__global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(SearchArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x;
+    const DevIdx& ix = a.ix;
+    const uint32_t nw = (ix.dim + 63u) / 64u;
+    SearchLds<NT> L;
+    TopK<NT> top;
+    [[maybe_unused]] uint8_t* end = carve_lds<NT>(smem, ix.dim, a.sort_cap, a.k, L, top);
+    if constexpr (WIDE) {
+        L.wfirst = (uint32_t*)carve(end, 4ull * kWideMaxDepth);
+        L.wdocs = (uint32_t*)carve(end, 4ull * kWideMaxDepth);
+        L.wnnz = (uint64_t*)carve(end, 8ull * kWideMaxDepth);
+    }
+    for (uint32_t i = tid; i < L.region_bytes / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
+    if (tid == 0) L.qv[0] = 0.0;
+    __syncthreads();
+
+    const uint32_t nq = a.nq_dev ? min(*a.nq_dev, a.nq) : a.nq;
+    // work items: queries, or at a list-major position the queries holding a
+    // cut list at this position
+    uint32_t it0 = 0, n_items = nq;
+    if constexpr (LIST) {
+        it0 = a.ls_seg[a.pos];
+        n_items = a.ls_seg[a.pos + 1] - it0;
+    }
+    for (;;) {
+        // ------------------------------------------------ next query
+        if (tid == 0) L.misc[15] = atomicAdd(a.queue, 1u);
         __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(L.misc[15]);
+        if (item >= n_items) break;
+        const uint32_t qi = __builtin_amdgcn_readfirstlane(LIST ? a.ls_items[it0 + item] : item);
+        top.which = 0;
+        top.hn = 0;
+
+        const Ingested in = ingest_query<NT, true>(a, L, qi, nw);
+        const uint32_t ncut = in.ncut, nvalid = in.nvalid, status = in.status;
+        const bool u8mode = in.u8mode;
 
         uint32_t ci0 = 0, ci1 = ncut;
         bool last = true;
@@ -722,10 +869,10 @@ __global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(Sear
         Counters C;
         if (u8mode) {
             LookU8 look{L.region, L.qv};
-            run_lists<NT, LookU8>(a, L, top, look, qi, ci0, ci1, nvalid, C);
+            run_lists<NT, LookU8, WIDE>(a, L, top, look, qi, ci0, ci1, nvalid, C);
         } else {
             LookBits look{L.bq};
-            run_lists<NT, LookBits>(a, L, top, look, qi, ci0, ci1, nvalid, C);
+            run_lists<NT, LookBits, WIDE>(a, L, top, look, qi, ci0, ci1, nvalid, C);
         }
         unsigned long long nnz_tot = 0;
         if (a.counters || LIST) {
@@ -764,17 +911,178 @@ __global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(Sear
                 c[6] = status; c[7] = ncut;
             }
         }
-        // restore the all-zero region
-        if (u8mode) {
-            for (uint32_t j = tid; j < nqe; j += NT) {
-                const uint32_t t = a.q_words[q0 + j] & 0xFFFFu;
-                if (t < ix.dim) L.region[t] = 0;
+        restore_region<NT>(a, L, in);
+    }
+}
+
+// Wide schedule, list pass: one (query, cut list) pair per item.  Scores
+// the summaries of all blocks of the list (step 2a), sorts them by (r desc,
+// block asc) (step 2b without the heap-dependent drop), stores the order,
+// and enqueues the first `depth` blocks for the evaluation pass.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_wide_lists(SearchArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x;
+    const DevIdx& ix = a.ix;
+    const uint32_t nw = (ix.dim + 63u) / 64u;
+    SearchLds<NT> L;
+    TopK<NT> top;
+    carve_lds<NT>(smem, ix.dim, a.sort_cap, a.k, L, top);
+    for (uint32_t i = tid; i < L.region_bytes / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
+    if (tid == 0) L.qv[0] = 0.0;
+    __syncthreads();
+    const uint32_t nq = a.nq_dev ? min(*a.nq_dev, a.nq) : a.nq;
+    const uint32_t n_items = nq * a.cmax;
+    for (;;) {
+        if (tid == 0) L.misc[15] = atomicAdd(a.wd_cnt + 0, 1u);
+        __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(L.misc[15]);
+        if (item >= n_items) break;
+        const uint32_t qi = item / a.cmax, ci = item - qi * a.cmax;
+        const Ingested in = ingest_query<NT, true>(a, L, qi, nw);
+        if (ci < in.ncut) {
+            const uint32_t t = L.cut[ci];
+            const uint32_t b0 = ix.list_off[t], nb = ix.list_off[t + 1] - b0;
+            if (nb) {
+                const uint64_t S0 = ix.blk_sum_off[b0], S1 = ix.blk_sum_off[b0 + nb];
+                if (in.u8mode)
+                    summary_sums<NT, LookU8>(ix, L, LookU8{L.region, L.qv}, b0, nb, S0, S1);
+                else
+                    summary_sums<NT, LookBits>(ix, L, LookBits{L.bq}, b0, nb, S0, S1);
+                uint32_t Pl = 2;
+                while (Pl < nb) Pl <<= 1;
+                for (uint32_t i = tid; i < Pl; i += NT) {
+                    if (i < nb) {
+                        L.r[i] = (float)((double)ix.blk_m[b0 + i] * L.A[i] + (double)ix.blk_delta[b0 + i] * L.B[i]);
+                        L.ord[i] = (uint16_t)i;
+                    } else {
+                        L.r[i] = -INFINITY;
+                        L.ord[i] = 0xFFFFu;
+                    }
+                }
+                __syncthreads();
+                sort_blocks<NT>(L, Pl);
+                const size_t lb = ((size_t)qi * a.cmax + ci) * a.sort_cap;
+                for (uint32_t i = tid; i < nb; i += NT) {
+                    a.wd_r[lb + i] = L.r[i];
+                    a.wd_ord[lb + i] = L.ord[i];
+                }
+                // speculated blocks: the first D0 of the order, each split into
+                // chunks of kWideChunk documents (one evaluation item each);
+                // the list keeps the longest prefix whose items fit the item
+                // capacity and whose blocks' chunk sets fit one traversal
+                // window (chunks * k <= NT candidates)
+                const uint32_t D0 = min(nb, a.depth);
+                uint32_t b = 0, n = 0, ch = 0;
+                if ((uint32_t)tid < D0) {
+                    b = b0 + L.ord[tid];
+                    n = ix.blk_post_off[b + 1] - ix.blk_post_off[b];
+                    ch = (n + kWideChunk - 1) / kWideChunk;
+                }
+                uint32_t T;
+                const uint32_t at = block_exscan<NT>(ch, L.scratch, &T);
+                if (tid == 0) L.misc[14] = atomicAdd(a.wd_cnt + 1, T);
+                __syncthreads();
+                const uint32_t base = L.misc[14];
+                const bool fits = (uint64_t)base + at + ch <= a.wd_icap && ch * a.k <= (uint32_t)NT;
+                if (tid == 0) L.misc[13] = D0;
+                __syncthreads();
+                if ((uint32_t)tid < D0 && !fits) atomicMin(&L.misc[13], (uint32_t)tid);
+                __syncthreads();
+                const uint32_t D = L.misc[13];
+                const uint32_t slot0 = (qi * a.cmax + ci) * a.depth;
+                if (tid == 0) a.wd_nspec[(size_t)qi * a.cmax + ci] = D;
+                if ((uint32_t)tid < D) {
+                    a.wd_first[slot0 + tid] = base + at;
+                    a.wd_nnz[slot0 + tid] = 0;
+                    a.wd_docs[slot0 + tid] = n;
+                    for (uint32_t j = 0; j < ch; ++j) a.wd_items[base + at + j] = make_uint4(b, j, slot0 + tid, 0);
+                } else if ((uint32_t)tid < D0) {
+                    // items reserved for blocks past the prefix: no-ops
+                    for (uint32_t j = 0; j < ch; ++j)
+                        if ((uint64_t)base + at + j < a.wd_icap) a.wd_items[base + at + j] = make_uint4(0xFFFFFFFFu, 0, 0, 0);
+                }
+            } else if (tid == 0) {
+                a.wd_nspec[(size_t)qi * a.cmax + ci] = 0;
             }
-        } else {
-            for (uint32_t i = tid; i < L.region_bytes / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
+        }
+        restore_region<NT>(a, L, in);
+    }
+}
+
+// Wide schedule, evaluation pass: one chunk of kWideChunk documents of a
+// speculated block per item.  Scores the chunk's documents exactly (step
+// 2c's gather) and stores their top-k beside the item; the block's
+// nonzeros are summed with an atomic add.  A workgroup keeps the lookup of
+// its last query.
+__global__ __launch_bounds__(kWideChunk) void k_wide_eval(SearchArgs a) {
+    constexpr int NT = kWideChunk;
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x;
+    const DevIdx& ix = a.ix;
+    const uint32_t nw = (ix.dim + 63u) / 64u;
+    SearchLds<NT> L;
+    TopK<NT> top;
+    carve_lds<NT>(smem, ix.dim, a.sort_cap, a.k, L, top);
+    for (uint32_t i = tid; i < L.region_bytes / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
+    if (tid == 0) L.qv[0] = 0.0;
+    __syncthreads();
+    const uint32_t n_items = min(a.wd_cnt[1], a.wd_icap);
+    const uint32_t per_query = a.cmax * a.depth;
+    const uint32_t k = a.k;
+    uint32_t cur = 0xFFFFFFFFu;
+    Ingested in{};
+    for (;;) {
+        if (tid == 0) L.misc[15] = atomicAdd(a.wd_cnt + 2, 1u);
+        __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(L.misc[15]);
+        if (item >= n_items) break;
+        const uint4 it = a.wd_items[item];
+        const uint32_t b = __builtin_amdgcn_readfirstlane(it.x);
+        if (b == 0xFFFFFFFFu) {  // a reserved item left unused
+            __syncthreads();
+            continue;
+        }
+        const uint32_t c = __builtin_amdgcn_readfirstlane(it.y), slot = __builtin_amdgcn_readfirstlane(it.z);
+        const uint32_t qi = slot / per_query;
+        if (qi != cur) {
+            if (cur != 0xFFFFFFFFu) restore_region<NT>(a, L, in);
+            in = ingest_query<NT, false>(a, L, qi, nw);
+            cur = qi;
+        }
+        top.which = 0;
+        top.hn = 0;
+        const uint32_t p0 = ix.blk_post_off[b], n = ix.blk_post_off[b + 1] - p0;
+        const uint32_t c0 = c * NT, m = min((uint32_t)NT, n - c0);
+        if (tid == 0) { L.wst[0] = 0; L.wst[1] = m; L.wp0[0] = p0; }
+        __syncthreads();
+        if (in.u8mode)
+            gather_and_score<NT, LookU8>(ix, L, LookU8{L.region, L.qv}, m, 1, c0);
+        else
+            gather_and_score<NT, LookBits>(ix, L, LookBits{L.bq}, m, 1, c0);
+        uint64_t nnz = 0;
+        fold_slot<NT>(L, top, m, -1, nnz);
+        const unsigned long long v = wave_sum((unsigned long long)nnz);
+        unsigned long long* red = (unsigned long long*)L.crs;  // the gather arrays are free here
+        if ((tid & (kWave - 1)) == 0) red[tid / kWave] = v;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long tot = 0;
+            for (int w = 0; w < NT / kWave; ++w) tot += red[w];
+            atomicAdd((unsigned long long*)(a.wd_nnz + slot), tot);
+        }
+        for (uint32_t i = tid; i < k; i += NT) {
+            const bool have = i < top.hn;
+            a.wd_ps[(size_t)item * k + i] = have ? top.hs()[i] : -INFINITY;
+            a.wd_pid[(size_t)item * k + i] = have ? top.hid()[i] : 0xFFFFFFFFu;
         }
         __syncthreads();
     }
+}
+
+__global__ void k_wide_reset(uint32_t* cnt, uint32_t* queue) {
+    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *queue = 0;
 }
 
 __global__ void k_reset_queue(uint32_t* queue) {
@@ -928,6 +1236,40 @@ hipError_t launch_search_positions(SearchArgs a, const ListSched& ls, uint32_t n
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (uint32_t r = 1; r < cmax && e == hipSuccess; ++r) e = position(r);
     return e;
+}
+
+hipError_t launch_search_wide(SearchArgs a, const WideSched& w, uint32_t nt, uint32_t grid, size_t smem,
+                              uint32_t grid_eval, size_t smem_eval, hipStream_t stream) {
+    if (a.nq == 0) return hipSuccess;
+    a.mode = kModeWide;
+    a.cmax = a.cut;
+    a.wd_r = w.r;
+    a.wd_ord = w.ord;
+    a.wd_nspec = w.nspec;
+    a.wd_items = w.items;
+    a.wd_icap = w.icap;
+    a.wd_cnt = w.cnt;
+    a.wd_first = w.first;
+    a.wd_docs = w.docs;
+    a.wd_nnz = w.nnz;
+    a.wd_ps = w.ps;
+    a.wd_pid = w.pid;
+    // the traversal's own window for blocks past the speculated ones
+    a.window = nt == 512 ? 16u : 8u;
+    const uint32_t g_lists = std::min<uint64_t>(grid, (uint64_t)a.nq * a.cmax);
+    const uint32_t g_eval = std::min<uint64_t>(grid_eval, w.icap);
+    const uint32_t g_fold = std::min<uint32_t>(grid, a.nq);
+    hipLaunchKernelGGL(k_wide_reset, dim3(1), dim3(64), 0, stream, w.cnt, a.queue);
+    if (nt == 512) {
+        hipLaunchKernelGGL(k_wide_lists<512>, dim3(g_lists), dim3(512), smem, stream, a);
+        hipLaunchKernelGGL(k_wide_eval, dim3(g_eval), dim3(kWideChunk), smem_eval, stream, a);
+        hipLaunchKernelGGL((k_search<512, false, true>), dim3(g_fold), dim3(512), smem + kWideMetaBytes, stream, a);
+    } else {
+        hipLaunchKernelGGL(k_wide_lists<256>, dim3(g_lists), dim3(256), smem, stream, a);
+        hipLaunchKernelGGL(k_wide_eval, dim3(g_eval), dim3(kWideChunk), smem_eval, stream, a);
+        hipLaunchKernelGGL((k_search<256, false, true>), dim3(g_fold), dim3(256), smem + kWideMetaBytes, stream, a);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace seismic_dev

@@ -52,10 +52,36 @@ struct SearchArgs {
     uint32_t* ls_hid;       // [nq * k] carried top-k ids
     uint32_t* ls_hn;        // [nq] carried top-k size
     uint64_t* ls_cnt;       // [nq * 6] carried counters 0..5
+    // Wide schedule (mode == kModeWide, small batches): a list pass scores
+    // and sorts the blocks of every (query, cut list) pair, an evaluation
+    // pass scores the first `depth` blocks of each sorted list, one
+    // workgroup per chunk of kWideChunk documents, keeping each chunk's k
+    // best documents; then the per-query traversal makes every prune
+    // decision in order, folding those stored top-k sets for the speculated
+    // blocks and gathering the others itself.  Strides: cmax cut lists per
+    // query, depth blocks per list.
+    uint32_t depth;         // blocks speculated per cut list (1..kWideMaxDepth)
+    float* wd_r;            // [nq * cmax * sort_cap] summary scores in (r desc, block asc) order
+    uint16_t* wd_ord;       // [nq * cmax * sort_cap] their block index within the list
+    uint32_t* wd_nspec;     // [nq * cmax] speculated blocks of each cut list (a prefix of the order)
+    uint4* wd_items;        // [wd_icap] evaluation items: (block, chunk, result slot, 0)
+    uint32_t wd_icap;       // item capacity
+    uint32_t* wd_cnt;       // [4]: list queue, items requested, evaluation queue
+    uint32_t* wd_first;     // [nq * cmax * depth] first item of each speculated block (its chunks follow)
+    uint32_t* wd_docs;      // [nq * cmax * depth] documents of each speculated block
+    uint64_t* wd_nnz;       // [nq * cmax * depth] and their nonzeros
+    float* wd_ps;           // [wd_icap * k] top-k scores of each item's chunk (-inf padded)
+    uint32_t* wd_pid;       // [wd_icap * k] and ids (0xFFFFFFFF padded)
 };
 
-constexpr uint32_t kModeQuery = 0, kModeList = 1;
+constexpr uint32_t kModeQuery = 0, kModeList = 1, kModeWide = 2;
 constexpr uint32_t kMaxPositions = 64;  // largest query_cut served by the list-major schedule
+constexpr uint32_t kWideMaxBatch = 256; // largest batch served by the wide schedule
+constexpr uint32_t kWideMaxCut = 32;    // largest query_cut served by the wide schedule
+constexpr uint32_t kWideMaxDepth = 64;  // largest speculation depth (blocks per cut list)
+constexpr uint32_t kWideMaxK = 64;      // largest k served by the wide schedule
+constexpr uint32_t kWideChunk = 256;    // documents per evaluation item (= its workgroup size)
+constexpr uint32_t kWideMetaBytes = 16 * kWideMaxDepth;  // extra LDS of the wide traversal
 
 // Device buffers of the list-major schedule for up to nq queries.
 struct ListSched {
@@ -73,6 +99,23 @@ struct ListSched {
     const uint32_t* term_rank = nullptr;  // [dim] rank of each list by block count, descending
 };
 
+// Device buffers of the wide schedule: room for cap queries, kWideMaxCut
+// cut lists of sort_cap blocks, kWideMaxDepth speculated blocks per list and
+// top-k sets of k entries.
+struct WideSched {
+    float* r = nullptr;
+    uint16_t* ord = nullptr;
+    uint32_t* nspec = nullptr;
+    uint4* items = nullptr;
+    uint32_t* cnt = nullptr;
+    uint32_t* first = nullptr;
+    uint32_t* docs = nullptr;
+    uint64_t* nnz = nullptr;
+    float* ps = nullptr;
+    uint32_t* pid = nullptr;
+    uint32_t cap = 0, sort_cap = 0, k = 0, icap = 0;
+};
+
 // nt = threads per workgroup (256 or 512); grid = number of persistent workgroups.
 size_t search_smem_bytes(uint32_t nt, uint32_t dim, uint32_t sort_cap, uint32_t k);
 hipError_t launch_search(const SearchArgs& a, uint32_t nt, uint32_t grid, size_t smem, hipStream_t stream);
@@ -80,6 +123,14 @@ hipError_t launch_search(const SearchArgs& a, uint32_t nt, uint32_t grid, size_t
 // construction and one launch per cut position.
 hipError_t launch_search_positions(SearchArgs a, const ListSched& ls, uint32_t nt, uint32_t grid, size_t smem,
                                 hipStream_t stream);
+// The same search in the wide schedule (a.cut in 1..kWideMaxCut, a.nq <=
+// w.cap, a.k <= w.k, a.depth in 1..kWideMaxDepth): list pass and traversal
+// as persistent grids of up to `grid` workgroups of nt threads (the
+// traversal with smem + kWideMetaBytes bytes of LDS), the
+// evaluation pass (one chunk of kWideChunk documents per item) of up to
+// grid_eval workgroups of kWideChunk threads with smem_eval bytes of LDS.
+hipError_t launch_search_wide(SearchArgs a, const WideSched& w, uint32_t nt, uint32_t grid, size_t smem,
+                              uint32_t grid_eval, size_t smem_eval, hipStream_t stream);
 int search_blocks_per_cu(uint32_t nt, size_t smem);  // resident workgroups per CU (0 on error)
 
 // Exact search over a full inverted index (term -> doc-ascending postings).

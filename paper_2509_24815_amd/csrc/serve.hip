@@ -38,7 +38,8 @@ struct Request {
     std::vector<float> scores;
 };
 
-constexpr uint32_t kSmallBatch = 256;  // the workspace's small-batch shapes cover up to this many queries
+constexpr uint32_t kTinyBatch = 64;    // the workspace's shapes for up to 64 queries (wide schedule by default)
+constexpr uint32_t kSmallBatch = 256;  // and for up to 256 queries
 
 struct Slot {
     hipStream_t stream = nullptr;
@@ -52,6 +53,7 @@ struct Slot {
     uint32_t* h_nq = nullptr;    // pinned
     seismic_batch_graph* graph = nullptr;
     seismic_batch_graph* graph_small = nullptr;  // for batches of <= kSmallBatch queries
+    seismic_batch_graph* graph_tiny = nullptr;   // for batches of <= kTinyBatch queries
     uint64_t* h_ptr = nullptr;   // pinned
     uint32_t* h_words = nullptr; // pinned
     uint32_t* h_ids = nullptr;   // pinned
@@ -87,6 +89,7 @@ namespace {
 void free_slot(Slot& s) {
     if (s.graph) seismic_graph_free(s.graph);
     if (s.graph_small) seismic_graph_free(s.graph_small);
+    if (s.graph_tiny) seismic_graph_free(s.graph_tiny);
     if (s.ws) seismic_workspace_free(s.ws);
     (void)hipFree(s.d_nq);
     (void)hipHostFree(s.h_nq);
@@ -125,12 +128,19 @@ int make_slot(seismic_server* sv, Slot& s) {
         seismic_csr q{nq, nnz, sv->index->h.dim, 1, s.d_ptr, s.d_words};
         rc = seismic_graph_create(sv->index, s.ws, &q, s.d_nq, &p.search, s.d_ids, s.d_scores, nullptr, &s.graph);
         if (rc) return rc;
-        // a second graph for small batches, captured in the workspace's shape
-        // for that size (one wider workgroup per query unless configured)
+        // graphs for small and tiny batches, captured in the workspace's
+        // shapes for those sizes (unless configured: one wider workgroup per
+        // query up to 256 queries, the wide schedule up to 64)
         if (nq > kSmallBatch) {
             seismic_csr qs{kSmallBatch, nnz, sv->index->h.dim, 1, s.d_ptr, s.d_words};
             rc = seismic_graph_create(sv->index, s.ws, &qs, s.d_nq, &p.search, s.d_ids, s.d_scores, nullptr,
                                       &s.graph_small);
+            if (rc) return rc;
+        }
+        if (nq > kTinyBatch) {
+            seismic_csr qt{kTinyBatch, nnz, sv->index->h.dim, 1, s.d_ptr, s.d_words};
+            rc = seismic_graph_create(sv->index, s.ws, &qt, s.d_nq, &p.search, s.d_ids, s.d_scores, nullptr,
+                                      &s.graph_tiny);
             if (rc) return rc;
         }
     }
@@ -145,7 +155,10 @@ int launch(seismic_server* sv, Slot& s, uint32_t nq, uint64_t nnz) {
     if (s.graph) {
         *s.h_nq = nq;
         HIP_TRY(hipMemcpyAsync(s.d_nq, s.h_nq, 4, hipMemcpyHostToDevice, s.stream));
-        int rc = seismic_graph_launch(nq <= kSmallBatch && s.graph_small ? s.graph_small : s.graph, s.stream);
+        seismic_batch_graph* g = s.graph;
+        if (nq <= kSmallBatch && s.graph_small) g = s.graph_small;
+        if (nq <= kTinyBatch && s.graph_tiny) g = s.graph_tiny;
+        int rc = seismic_graph_launch(g, s.stream);
         if (rc) return rc;
     } else {
         seismic_csr q{nq, nnz, sv->index->h.dim, 1, s.d_ptr, s.d_words};
