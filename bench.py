@@ -187,6 +187,41 @@ def device_collection(torch, synth, n_docs, mean, chunk=2_000_000):
     return rp_dev, w_dev, nnz
 
 
+def lone_query_latency(binding, ix, q_rp, q_w, dim, n_rows, k, cut, hf, stream, n=64, reps=3):
+    """Device time of single-query searches (HIP events on the launch
+    stream): n queries spread over the batch, each searched alone `reps`
+    times after a warm-up, in a new workspace's shape for one query (the
+    wide schedule) and in the query-major shape (512 threads, window 16)."""
+    import torch
+    out = {"queries": n}
+    picks = np.linspace(0, n_rows - 1, n).astype(np.int64)
+    ids = torch.empty((1, k), dtype=torch.int32, device=q_w.device)
+    sc = torch.empty((1, k), dtype=torch.float32, device=q_w.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, shape in (("wide", None), ("query_major", (512, 0, 16, 0))):
+        ws = binding.seismic_workspace_create(ix.handle, 1, k)
+        try:
+            if shape:
+                binding.seismic_workspace_set_config(ws, *shape)
+            ts = []
+            for i in picks:
+                q = binding.device_csr(q_rp[int(i):int(i) + 2], q_w, dim)  # one row, absolute offsets
+                binding.seismic_search_batch(ix.handle, ws, q, k, cut, hf, ids, sc, stream=stream)
+                e0.record(stream)
+                for _ in range(reps):
+                    binding.seismic_search_batch(ix.handle, ws, q, k, cut, hf, ids, sc, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1) / reps)
+            ts = np.asarray(ts)
+            out[name] = {"launch": binding.seismic_workspace_get_config(ws, 1),
+                         "p50_ms": round(float(np.percentile(ts, 50)), 3),
+                         "p99_ms": round(float(np.percentile(ts, 99)), 3), "mean_ms": round(float(ts.mean()), 3)}
+        finally:
+            binding.seismic_workspace_free(ws)
+    return out
+
+
 def serve_run(binding, ix, qs, rate, seconds, k, cut, hf, probe, tau, max_batch=1024, slots=4):
     """Open-loop Poisson arrivals at `rate` queries/s for `seconds` (queries
     cycle through the batch), served by the library's serving loop.
@@ -618,9 +653,13 @@ def main():
             refined["with_learned_probe"] = both
         log(f"[bench] refined {refined}")
 
-    # serving loop: Poisson arrivals, continuous batching over 4 slots
+    # lone-query latency (device time), then the serving loop: Poisson
+    # arrivals, continuous batching over 4 slots
     serving = None
+    lone = None
     if not args.no_serve:
+        lone = lone_query_latency(binding, ix, q_rp, q_w, qs.dim, nq, k, cut, chosen, stream)
+        log(f"[bench] lone-query latency {lone}")
         serving = {}
         rates = (5000.0, 20000.0, 50000.0)
         forms = [("heap_factor_rule", None, 0.0)]
@@ -701,6 +740,7 @@ def main():
                    "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
                    "sweep": sweep, "learned_probe": learned, "knn_refined": refined, "grid": grid,
                    "locality_order": locality},
+        "lone_query_latency": lone,
         "serving": serving,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
