@@ -72,6 +72,12 @@ struct SearchLds {
     uint32_t* wfirst;  // [kWideMaxDepth] first evaluation item
     uint32_t* wdocs;   // [kWideMaxDepth] documents
     uint64_t* wnnz;    // [kWideMaxDepth] nonzeros
+    // and every cut list's header, loaded at once
+    uint32_t* wl_b0;   // [kWideMaxCut] first block
+    uint32_t* wl_nb;   // [kWideMaxCut] blocks
+    uint32_t* wl_D;    // [kWideMaxCut] speculated blocks
+    uint64_t* wl_S0;   // [kWideMaxCut] summary entries [S0, S1)
+    uint64_t* wl_S1;   // [kWideMaxCut]
 };
 
 __host__ __device__ inline uint32_t r16u(uint64_t x) { return (uint32_t)((x + 15) & ~uint64_t(15)); }
@@ -469,9 +475,29 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
     const int tid = threadIdx.x;
     const DevIdx& ix = a.ix;
     const uint32_t W = a.window;
+    if constexpr (WIDE) {
+        // the headers of all cut lists in one round of loads
+        for (uint32_t ci = ci0 + tid; ci < ci1; ci += NT) {
+            const uint32_t t = L.cut[ci];
+            const uint32_t b0 = ix.list_off[t], b1 = ix.list_off[t + 1];
+            L.wl_b0[ci] = b0;
+            L.wl_nb[ci] = b1 - b0;
+            L.wl_S0[ci] = ix.blk_sum_off[b0];
+            L.wl_S1[ci] = ix.blk_sum_off[b1];
+            L.wl_D[ci] = b1 > b0 ? a.wd_nspec[(size_t)qi * a.cmax + ci] : 0u;
+        }
+        __syncthreads();
+    }
     for (uint32_t ci = ci0; ci < ci1; ++ci) {
         const uint32_t t = L.cut[ci];
-        const uint32_t b0 = ix.list_off[t], b1 = ix.list_off[t + 1];
+        uint32_t b0, b1;
+        if constexpr (WIDE) {
+            b0 = L.wl_b0[ci];
+            b1 = b0 + L.wl_nb[ci];
+        } else {
+            b0 = ix.list_off[t];
+            b1 = ix.list_off[t + 1];
+        }
         const uint32_t nb = b1 - b0;
         if (tid == 0 && ci < a.prefix_stride) {
             if (a.list_term) a.list_term[(size_t)qi * a.prefix_stride + ci] = t;
@@ -482,7 +508,14 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
             continue;
         }
         // ---------------------------------------- a. summary scores
-        const uint64_t S0 = ix.blk_sum_off[b0], S1 = ix.blk_sum_off[b1];
+        uint64_t S0, S1;
+        if constexpr (WIDE) {
+            S0 = L.wl_S0[ci];
+            S1 = L.wl_S1[ci];
+        } else {
+            S0 = ix.blk_sum_off[b0];
+            S1 = ix.blk_sum_off[b1];
+        }
         C.sum += S1 - S0;
         C.blocks += nb;
         [[maybe_unused]] const float* wr = nullptr;     // WIDE: sorted scores of this list
@@ -493,7 +526,7 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
             const size_t lb = ((size_t)qi * a.cmax + ci) * a.sort_cap;
             wr = a.wd_r + lb;
             wo = a.wd_ord + lb;
-            D = a.wd_nspec[(size_t)qi * a.cmax + ci];
+            D = L.wl_D[ci];
             wslot = ((size_t)qi * a.cmax + ci) * a.depth;
         } else {
             summary_sums<NT, Look>(ix, L, look, b0, nb, S0, S1);
@@ -827,6 +860,11 @@ __global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(Sear
         L.wfirst = (uint32_t*)carve(end, 4ull * kWideMaxDepth);
         L.wdocs = (uint32_t*)carve(end, 4ull * kWideMaxDepth);
         L.wnnz = (uint64_t*)carve(end, 8ull * kWideMaxDepth);
+        L.wl_b0 = (uint32_t*)carve(end, 4ull * kWideMaxCut);
+        L.wl_nb = (uint32_t*)carve(end, 4ull * kWideMaxCut);
+        L.wl_D = (uint32_t*)carve(end, 4ull * kWideMaxCut);
+        L.wl_S0 = (uint64_t*)carve(end, 8ull * kWideMaxCut);
+        L.wl_S1 = (uint64_t*)carve(end, 8ull * kWideMaxCut);
     }
     for (uint32_t i = tid; i < L.region_bytes / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
     if (tid == 0) L.qv[0] = 0.0;
