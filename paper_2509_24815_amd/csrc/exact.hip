@@ -17,6 +17,7 @@ namespace seismic_dev {
 
 constexpr int kBlock = 256;
 constexpr uint32_t kRange = 2048;
+constexpr uint32_t kPost = 8;  // postings in flight per thread
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint8_t* xbump(uint8_t*& p, size_t bytes) {
@@ -117,15 +118,32 @@ __global__ __launch_bounds__(kBlock) void k_exact(ExactArgs a) {
                 while (hi - lo > 1) { uint32_t mid = (lo + hi) >> 1; if (pfx[mid] <= (uint32_t)tid) lo = mid; else hi = mid; }
                 j = lo;
             }
-            for (uint32_t i = tid; i < T; i += kBlock) {
-                while (pfx[j + 1] <= i) ++j;
-                const uint32_t o = i - pfx[j];
-                const uint64_t pos = cur[j] + o;
-                const uint32_t d = a.csc_doc[pos];
-                if (d < e) {
-                    atomicAdd(&acc[d - s], (double)(qv[j] * half_bits_to_float(a.csc_val[pos])));
-                } else {
-                    atomicMin(&fge[j], o);
+            // kPost postings per thread per step: all their loads are issued
+            // before any is consumed
+            for (uint32_t i0 = tid; i0 < T; i0 += kBlock * kPost) {
+                uint32_t dd[kPost], jj[kPost], oo[kPost];
+                uint16_t vv[kPost];
+#pragma unroll
+                for (uint32_t u = 0; u < kPost; ++u) {
+                    const uint32_t i = i0 + u * kBlock;
+                    dd[u] = kInf;
+                    if (i < T) {
+                        while (pfx[j + 1] <= i) ++j;
+                        jj[u] = j;
+                        oo[u] = i - pfx[j];
+                        const uint64_t pos = cur[j] + oo[u];
+                        dd[u] = a.csc_doc[pos];
+                        vv[u] = a.csc_val[pos];
+                    }
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kPost; ++u) {
+                    if (i0 + u * kBlock >= T) break;
+                    if (dd[u] < e) {
+                        atomicAdd(&acc[dd[u] - s], (double)(qv[jj[u]] * half_bits_to_float(vv[u])));
+                    } else {
+                        atomicMin(&fge[jj[u]], oo[u]);
+                    }
                 }
             }
             __syncthreads();
