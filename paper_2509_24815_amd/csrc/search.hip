@@ -20,7 +20,7 @@
 //         sorted in LDS by (r desc, block asc) with a bitonic network;
 //      c. traversal in that order: up to W consecutive blocks (at most NT
 //         documents) are gathered at once - a thread per document fetches
-//         its posting and row offsets, then groups of 8 lanes stream whole
+//         its posting and row offsets, then groups of 4 lanes stream whole
 //         rows as 16-byte loads and accumulate exact products in fp64 - and
 //         the blocks are then replayed one by one: a block is evaluated
 //         unless the heap is full and r * heap_factor < heap.min, which ends
@@ -38,7 +38,8 @@
 namespace seismic_dev {
 
 constexpr uint32_t kUnroll = 2;       // 16-byte row loads in flight per document and lane
-constexpr uint32_t kLanesPerDoc = 8;  // lanes sharing one row
+constexpr uint32_t kLanesPerDoc = 4;  // lanes sharing one row
+constexpr uint32_t kDocsPerGroup = 2; // rows a group of lanes streams at a time
 constexpr uint32_t kSumUnroll = 2;    // summary groups in flight per thread
 constexpr uint32_t kMaxSlots = 255;   // distinct query terms served by the u8 slot table
 
@@ -255,31 +256,34 @@ __device__ inline void gather_and_score_t(const DevIdx& ix, const SearchLds<NT>&
     }
     __syncthreads();
     const uint32_t* src = BR ? ix.brow : ix.words;
-    constexpr uint32_t G = kLanesPerDoc, NG = NT / kLanesPerDoc;
+    constexpr uint32_t G = kLanesPerDoc, NG = NT / kLanesPerDoc, H = kDocsPerGroup;
     const uint32_t grp = (uint32_t)tid / G, gl = (uint32_t)tid % G;
-    for (uint32_t base = grp; base < tot; base += 2 * NG) {
-        uint64_t g0[2];
-        uint32_t ng[2], head[2], len[2];
-        double acc[2] = {0.0, 0.0};
+    for (uint32_t base = grp; base < tot; base += H * NG) {
+        uint64_t g0[H];
+        uint32_t ng[H], head[H], len[H];
+        double acc[H];
+        uint32_t ngmax = 0;
 #pragma unroll
-        for (uint32_t h = 0; h < 2; ++h) {
+        for (uint32_t h = 0; h < H; ++h) {
             const uint32_t t = base + h * NG;
             const uint64_t rs = t < tot ? L.crs[t] : 0;
             len[h] = t < tot ? L.clen[t] : 0;
             g0[h] = rs >> 2;
             head[h] = (uint32_t)(rs & 3);  // row start inside its first group
             ng[h] = len[h] ? (uint32_t)(((rs + len[h] + 3) >> 2) - g0[h]) : 0u;
+            ngmax = max(ngmax, ng[h]);
+            acc[h] = 0.0;
         }
-        for (uint32_t k = gl; k < ng[0] || k < ng[1]; k += kUnroll * G) {
-            uint4 w[2][kUnroll];
+        for (uint32_t k = gl; k < ngmax; k += kUnroll * G) {
+            uint4 w[H][kUnroll];
 #pragma unroll
-            for (uint32_t h = 0; h < 2; ++h)
+            for (uint32_t h = 0; h < H; ++h)
 #pragma unroll
                 for (uint32_t u = 0; u < kUnroll; ++u)
                     w[h][u] = (k + u * G < ng[h]) ? *(const uint4*)(src + ((g0[h] + k + u * G) << 2))
                                                  : make_uint4(0, 0, 0, 0);
 #pragma unroll
-            for (uint32_t h = 0; h < 2; ++h)
+            for (uint32_t h = 0; h < H; ++h)
 #pragma unroll
                 for (uint32_t u = 0; u < kUnroll; ++u) {
                     // position of the group's first word relative to the row start
@@ -293,11 +297,12 @@ __device__ inline void gather_and_score_t(const DevIdx& ix, const SearchLds<NT>&
                     }
                 }
         }
-        acc[0] = group_sum<double, G>(acc[0]);
-        acc[1] = group_sum<double, G>(acc[1]);
+#pragma unroll
+        for (uint32_t h = 0; h < H; ++h) acc[h] = group_sum<double, G>(acc[h]);
         if (gl == 0) {
-            if (base < tot) L.cacc[base] = acc[0];
-            if (base + NG < tot) L.cacc[base + NG] = acc[1];
+#pragma unroll
+            for (uint32_t h = 0; h < H; ++h)
+                if (base + h * NG < tot) L.cacc[base + h * NG] = acc[h];
         }
     }
     __syncthreads();
