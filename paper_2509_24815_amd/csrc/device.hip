@@ -203,9 +203,12 @@ int ensure_wide_sched(seismic_workspace* ws) {
 
 // Does the wide schedule serve this batch (buffers present, sizes within them)?
 bool wide_applies(const seismic_workspace* ws, uint64_t nq, const seismic_search_params* params, uint32_t nt) {
-    const size_t smem = seismic_dev::search_smem_bytes(nt, ws->index->h.dim, ws->index->dev->sort_cap, params->k);
+    const uint32_t dim = ws->index->h.dim, P = ws->index->dev->sort_cap;
+    const size_t smem = seismic_dev::search_smem_bytes(nt, dim, P, params->k);
+    const size_t smem_lists = seismic_dev::search_smem_bytes(seismic_dev::kWideListThreads, dim, P, params->k);
     return ws->wd.r && nq <= ws->wd.cap && params->query_cut >= 1 && params->query_cut <= seismic_dev::kWideMaxCut &&
-           params->k <= ws->wd.k && smem + seismic_dev::kWideMetaBytes <= ws->index->dev->smem_limit;
+           params->k <= ws->wd.k && smem + seismic_dev::kWideMetaBytes <= ws->index->dev->smem_limit &&
+           smem_lists <= ws->index->dev->smem_limit;
 }
 
 int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64_t* q_ptr, const uint32_t* q_words,
@@ -250,7 +253,10 @@ int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64
         const size_t smem_eval = seismic_dev::search_smem_bytes(256, index->h.dim, index->dev->sort_cap, params->k);
         const int per_cu_eval = seismic_dev::search_blocks_per_cu(256, smem_eval);
         if (per_cu_eval < 1) return fail(SEISMIC_EHIP, "search: kernel does not fit on a CU (%zu bytes of LDS)", smem_eval);
+        const size_t smem_lists = seismic_dev::search_smem_bytes(seismic_dev::kWideListThreads, index->h.dim,
+                                                                 index->dev->sort_cap, params->k);
         HIP_TRY(seismic_dev::launch_search_wide(a, ws->wd, nt, (uint32_t)per_cu * (uint32_t)ws->n_cu, smem,
+                                                2u * (uint32_t)ws->n_cu, smem_lists,
                                                 (uint32_t)per_cu_eval * (uint32_t)ws->n_cu, smem_eval, st));
     } else if (cfg.schedule == 1 && ws->ls.cut && index->dev->term_rank && params->query_cut >= 1 &&
         params->query_cut <= seismic_dev::kMaxPositions) {

@@ -1014,7 +1014,7 @@ __global__ __launch_bounds__(NT) void k_wide_lists(SearchArgs a) {
                 // chunks of kWideChunk documents (one evaluation item each);
                 // the list keeps the longest prefix whose items fit the item
                 // capacity and whose blocks' chunk sets fit one traversal
-                // window (chunks * k <= NT candidates)
+                // window (chunks * k <= wd_nt candidates)
                 const uint32_t D0 = min(nb, a.depth);
                 uint32_t b = 0, n = 0, ch = 0;
                 if ((uint32_t)tid < D0) {
@@ -1027,7 +1027,7 @@ __global__ __launch_bounds__(NT) void k_wide_lists(SearchArgs a) {
                 if (tid == 0) L.misc[14] = atomicAdd(a.wd_cnt + 1, T);
                 __syncthreads();
                 const uint32_t base = L.misc[14];
-                const bool fits = (uint64_t)base + at + ch <= a.wd_icap && ch * a.k <= (uint32_t)NT;
+                const bool fits = (uint64_t)base + at + ch <= a.wd_icap && ch * a.k <= a.wd_nt;
                 if (tid == 0) L.misc[13] = D0;
                 __syncthreads();
                 if ((uint32_t)tid < D0 && !fits) atomicMin(&L.misc[13], (uint32_t)tid);
@@ -1218,6 +1218,7 @@ __global__ __launch_bounds__(256) void k_items_scatter(const uint32_t* nq_dev, u
 }
 
 size_t search_smem_bytes(uint32_t nt, uint32_t dim, uint32_t sort_cap, uint32_t k) {
+    if (nt == 1024) return search_smem_bytes_t<1024>(dim, sort_cap, k);
     return nt == 512 ? search_smem_bytes_t<512>(dim, sort_cap, k) : search_smem_bytes_t<256>(dim, sort_cap, k);
 }
 
@@ -1282,7 +1283,8 @@ hipError_t launch_search_positions(SearchArgs a, const ListSched& ls, uint32_t n
 }
 
 hipError_t launch_search_wide(SearchArgs a, const WideSched& w, uint32_t nt, uint32_t grid, size_t smem,
-                              uint32_t grid_eval, size_t smem_eval, hipStream_t stream) {
+                              uint32_t grid_lists, size_t smem_lists, uint32_t grid_eval, size_t smem_eval,
+                              hipStream_t stream) {
     if (a.nq == 0) return hipSuccess;
     a.mode = kModeWide;
     a.cmax = a.cut;
@@ -1299,16 +1301,17 @@ hipError_t launch_search_wide(SearchArgs a, const WideSched& w, uint32_t nt, uin
     a.wd_pid = w.pid;
     // the traversal's own window for blocks past the speculated ones
     a.window = nt == 512 ? 16u : 8u;
-    const uint32_t g_lists = std::min<uint64_t>(grid, (uint64_t)a.nq * a.cmax);
+    a.wd_nt = nt;
+    const uint32_t g_lists = std::min<uint64_t>(grid_lists, (uint64_t)a.nq * a.cmax);
     const uint32_t g_eval = std::min<uint64_t>(grid_eval, w.icap);
     const uint32_t g_fold = std::min<uint32_t>(grid, a.nq);
     hipLaunchKernelGGL(k_wide_reset, dim3(1), dim3(64), 0, stream, w.cnt, a.queue);
     if (nt == 512) {
-        hipLaunchKernelGGL(k_wide_lists<512>, dim3(g_lists), dim3(512), smem, stream, a);
+        hipLaunchKernelGGL(k_wide_lists<kWideListThreads>, dim3(g_lists), dim3(kWideListThreads), smem_lists, stream, a);
         hipLaunchKernelGGL(k_wide_eval, dim3(g_eval), dim3(kWideChunk), smem_eval, stream, a);
         hipLaunchKernelGGL((k_search<512, false, true>), dim3(g_fold), dim3(512), smem + kWideMetaBytes, stream, a);
     } else {
-        hipLaunchKernelGGL(k_wide_lists<256>, dim3(g_lists), dim3(256), smem, stream, a);
+        hipLaunchKernelGGL(k_wide_lists<kWideListThreads>, dim3(g_lists), dim3(kWideListThreads), smem_lists, stream, a);
         hipLaunchKernelGGL(k_wide_eval, dim3(g_eval), dim3(kWideChunk), smem_eval, stream, a);
         hipLaunchKernelGGL((k_search<256, false, true>), dim3(g_fold), dim3(256), smem + kWideMetaBytes, stream, a);
     }

@@ -61,6 +61,7 @@ struct SearchArgs {
     // blocks and gathering the others itself.  Strides: cmax cut lists per
     // query, depth blocks per list.
     uint32_t depth;         // blocks speculated per cut list (1..kWideMaxDepth)
+    uint32_t wd_nt;         // threads of the traversal (its window holds at most wd_nt candidates)
     float* wd_r;            // [nq * cmax * sort_cap] summary scores in (r desc, block asc) order
     uint16_t* wd_ord;       // [nq * cmax * sort_cap] their block index within the list
     uint32_t* wd_nspec;     // [nq * cmax] speculated blocks of each cut list (a prefix of the order)
@@ -124,13 +125,16 @@ hipError_t launch_search(const SearchArgs& a, uint32_t nt, uint32_t grid, size_t
 hipError_t launch_search_positions(SearchArgs a, const ListSched& ls, uint32_t nt, uint32_t grid, size_t smem,
                                 hipStream_t stream);
 // The same search in the wide schedule (a.cut in 1..kWideMaxCut, a.nq <=
-// w.cap, a.k <= w.k, a.depth in 1..kWideMaxDepth): list pass and traversal
-// as persistent grids of up to `grid` workgroups of nt threads (the
-// traversal with smem + kWideMetaBytes bytes of LDS), the
-// evaluation pass (one chunk of kWideChunk documents per item) of up to
-// grid_eval workgroups of kWideChunk threads with smem_eval bytes of LDS.
+// w.cap, a.k <= w.k, a.depth in 1..kWideMaxDepth): the list pass as a
+// persistent grid of up to grid_lists workgroups of kWideListThreads
+// threads (smem_lists bytes of LDS), the evaluation pass (one chunk of
+// kWideChunk documents per item) of up to grid_eval workgroups of
+// kWideChunk threads (smem_eval), the traversal of up to `grid` workgroups
+// of nt threads (smem + kWideMetaBytes).
+constexpr uint32_t kWideListThreads = 1024;
 hipError_t launch_search_wide(SearchArgs a, const WideSched& w, uint32_t nt, uint32_t grid, size_t smem,
-                              uint32_t grid_eval, size_t smem_eval, hipStream_t stream);
+                              uint32_t grid_lists, size_t smem_lists, uint32_t grid_eval, size_t smem_eval,
+                              hipStream_t stream);
 int search_blocks_per_cu(uint32_t nt, size_t smem);  // resident workgroups per CU (0 on error)
 
 // Exact search over a full inverted index (term -> doc-ascending postings).
