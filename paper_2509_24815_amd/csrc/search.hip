@@ -338,6 +338,27 @@ __device__ inline void fold_slot(const SearchLds<NT>& L, TopK<NT>& top, uint32_t
     if (nc) top.merge(nc);
 }
 
+// fold_slot for the wide traversal's stored candidate sets (no nonzero
+// counts): returns after one barrier when no candidate of the slot enters.
+template <int NT>
+__device__ inline void fold_slot_sparse(const SearchLds<NT>& L, TopK<NT>& top, uint32_t tot, int slot) {
+    const int tid = threadIdx.x;
+    bool cand = false;
+    float sc = 0.0f;
+    uint32_t d = 0;
+    if ((uint32_t)tid < tot && (slot < 0 || L.cslot[tid] == (uint32_t)slot)) {
+        sc = (float)L.cacc[tid];
+        d = L.cdoc[tid];
+        cand = top.admits(sc, d);
+    }
+    if (!__syncthreads_or(cand ? 1 : 0)) return;
+    uint32_t nc;
+    const uint32_t at = block_exscan<NT>(cand ? 1u : 0u, L.scratch, &nc);
+    if (cand) { top.cs[at] = sc; top.cid[at] = d; }
+    __syncthreads();
+    top.merge(nc);
+}
+
 // Learned-probe decision for one block.  Kept out of line (the search's
 // register budget is set by its gather phase); the parameter pointer is
 // made wave-uniform and read through the constant address space, so the
@@ -592,32 +613,62 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
                 // of their documents (a document outside its chunk's k best
                 // has k better ones in the same block)
                 const uint32_t k = a.k;
-                // blocks while their candidates fit (a speculated block alone always does)
-                while (nwb < kMaxW && pos + nwb < nsurv && L.ord[pos + nwb] < D) {
-                    const uint32_t c = (L.wdocs[L.ord[pos + nwb]] + kWideChunk - 1) / kWideChunk * k;
-                    if (nwb > 0 && tot + c > (uint32_t)NT) break;
-                    tot += c;
-                    ++nwb;
-                }
-                if ((uint32_t)tid < tot) {
-                    uint32_t s = 0, run = 0;
-                    for (;; ++s) {
-                        const uint32_t c = (L.wdocs[L.ord[pos + s]] + kWideChunk - 1) / kWideChunk * k;
-                        if ((uint32_t)tid < run + c) break;
-                        run += c;
+                // wave 0 forms the window: consecutive speculated blocks while
+                // their candidates fit (a speculated block alone always does),
+                // the first candidate of each (wst), their sizes and items
+                if (tid < kWave) {
+                    const uint32_t s = (uint32_t)tid;
+                    const bool in = s < kMaxW && pos + s < nsurv;
+                    const uint32_t o = in ? L.ord[pos + s] : 0u;
+                    const bool sp = in && o < D;
+                    const uint32_t c = sp ? (L.wdocs[o] + kWideChunk - 1) / kWideChunk * k : 0u;
+                    const uint64_t nsp = __ballot(!sp);
+                    const uint32_t run = nsp ? (uint32_t)__ffsll((unsigned long long)nsp) - 1u : (uint32_t)kWave;
+                    uint32_t incl = c;
+#pragma unroll
+                    for (int d = 1; d < kWave; d <<= 1) {
+                        const uint32_t y = __shfl_up(incl, d, kWave);
+                        if (s >= (uint32_t)d) incl += y;
                     }
-                    const size_t e = (size_t)L.wfirst[L.ord[pos + s]] * k + ((uint32_t)tid - run);
+                    const bool take = s < run && (s == 0 || incl <= (uint32_t)NT);
+                    const uint32_t n = (uint32_t)__popcll(__ballot(take));
+                    const uint32_t total = __shfl(incl, (int)(n > 0 ? n - 1 : 0), kWave);
+                    const uint64_t nnz_s = take ? L.wnnz[o] : 0ull;
+                    const uint32_t docs_s = take ? L.wdocs[o] : 0u;
+                    if (take) {
+                        L.wst[s] = incl - c;
+                        L.wlen[s] = docs_s;
+                        L.crs[s] = nnz_s;
+                        L.wp0[s] = L.wfirst[o];
+                    }
+                    const unsigned long long wn = wave_sum((unsigned long long)nnz_s);
+                    const uint32_t wd = (uint32_t)wave_sum((unsigned long long)docs_s);
+                    if (s == 0) {
+                        L.wst[n] = total;
+                        L.misc[12] = n;
+                        L.misc[13] = total;
+                        L.misc[14] = wd;
+                        L.crs[kMaxW] = wn;
+                    }
+                }
+                __syncthreads();
+                nwb = __builtin_amdgcn_readfirstlane(L.misc[12]);
+                tot = __builtin_amdgcn_readfirstlane(L.misc[13]);
+                wdocs = L.misc[14];
+                wnnz = L.crs[kMaxW];
+                if ((uint32_t)tid < tot) {
+                    uint32_t lo = 0, hi = nwb;  // last block with wst <= tid
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (L.wst[mid] <= (uint32_t)tid) lo = mid; else hi = mid;
+                    }
+                    const size_t e = (size_t)L.wp0[lo] * k + ((uint32_t)tid - L.wst[lo]);
                     L.cacc[tid] = (double)a.wd_ps[e];
                     L.cdoc[tid] = a.wd_pid[e];
                     L.clen[tid] = 0;
-                    L.cslot[tid] = (uint8_t)s;
-                }
-                if ((uint32_t)tid < nwb) {
-                    L.wlen[tid] = L.wdocs[L.ord[pos + tid]];
-                    L.crs[tid] = L.wnnz[L.ord[pos + tid]];
+                    L.cslot[tid] = (uint8_t)lo;
                 }
                 __syncthreads();
-                for (uint32_t s = 0; s < nwb; ++s) { wdocs += L.wlen[s]; wnnz += L.crs[s]; }
             } else {
             if ((uint32_t)tid < W && pos + tid < nsurv) {
                 uint32_t b;
@@ -678,9 +729,15 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
                 } else {
                     C.docs += tot;
                 }
-                fold_slot<NT>(L, top, tot, -1, C.nnz);
+                if (WIDE && spec)
+                    fold_slot_sparse<NT>(L, top, tot, -1);
+                else
+                    fold_slot<NT>(L, top, tot, -1, C.nnz);
                 folded = true;
-            } else if (nwb > 1 && top.full() && (double)L.r[pos] * (double)a.hf >= (double)top.min_score()) {
+            } else if (nwb > 1 && top.full() && (double)L.r[pos] * (double)a.hf >= (double)top.min_score() &&
+                       (!WIDE || (double)L.r[pos + nwb - 1] * (double)a.hf >= (double)top.min_score())) {
+                // (wide: skipped when the last block already fails against the
+                // current minimum, since the merged one is not smaller)
                 uint64_t nnz = 0;
                 const uint32_t ns = fold_window_pending<NT>(L, top, tot, nnz);
                 const float m2 = ns ? top.pending_min() : top.min_score();
@@ -707,7 +764,10 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
                 C.docs += L.wlen[s];
                 if constexpr (WIDE)
                     if (spec && tid == 0) C.nnz += L.crs[s];
-                fold_slot<NT>(L, top, tot, (int)s, C.nnz);
+                if (WIDE && spec)
+                    fold_slot_sparse<NT>(L, top, tot, (int)s);
+                else
+                    fold_slot<NT>(L, top, tot, (int)s, C.nnz);
             }
             pos += stop ? 0u : nwb;
             __syncthreads();
