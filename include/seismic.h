@@ -240,19 +240,22 @@ void seismic_workspace_free(seismic_workspace* ws);
    visiting the same list run together and share its blocks in the caches;
    each query's top-k is carried between positions; used when 1 <=
    query_cut <= 64, else query-major), 2 wide (for small batches: one
-   workgroup per (query, cut list) scores and sorts the list's summaries,
-   one workgroup per block evaluates the first `window` blocks (1..64) of
-   every sorted list, keeping each block's k best documents, then one
-   workgroup per query replays Algorithm 2's prune decisions in order over
-   those stored sets, gathering any later block itself; used when the batch
-   has at most 256 queries, 1 <= query_cut <= 32 and k <= 64, else
-   query-major).  Results never depend on the shape.
+   workgroup per (query, cut list) scores and sorts the list's summaries;
+   the first `window` blocks (1..64) of every sorted list are cut into
+   chunks of 256 documents and one workgroup per chunk scores it and keeps
+   its k best documents; then one workgroup per query replays Algorithm 2's
+   prune decisions in order over those stored sets, gathering any later
+   block itself; used when the batch has at most 256 queries, 1 <=
+   query_cut <= 32 and k <= 64, else query-major).  Results never depend on
+   the shape.
    Selecting schedule 1 (set_config, or the autotuner trying it) allocates
    the workspace's list-major buffers once: about max_queries * (450 + 8 *
    max_k) bytes plus 256 bytes per index term.  Schedule 2 allocates its
-   buffers once for c = min(max_queries, 256) queries: about c * 32 *
-   (6 * sort_cap + 64 * (20 + 8 * min(max_k, 64))) bytes, sort_cap being the
-   power of two at or above the index's longest list in blocks.  EINVAL for
+   buffers once for c = min(max_queries, 256) queries and k' = min(max_k,
+   64): c * 32 * (6 * sort_cap + 1028) bytes for the sorted lists and
+   speculated blocks (sort_cap: the power of two at or above the index's
+   longest list in blocks) plus n * (16 + 8 * k') bytes for n = min(4 * c *
+   2048, max(c * 2048, 2^25 / k')) chunk items and their top-k sets.  EINVAL for
    unsupported shapes, ENOMEM if those buffers do not fit. */
 typedef struct {
     uint32_t threads;
