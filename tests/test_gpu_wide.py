@@ -2,7 +2,8 @@
 search result, prefix length, counter and trace entry equal to the oracle's
 and to the query-major schedule's — over cut/heap_factor/k points,
 speculation depths from 1 to 64, both workgroup sizes, blocks larger than a
-workgroup, long queries (bitmap lookup), the learned probe, the alpha_q cut,
+workgroup, a batch that needs more evaluation items than the workspace
+holds, long queries (bitmap lookup), the learned probe, the alpha_q cut,
 refinement, edge queries, a device-side batch size inside graph replays,
 the fallbacks outside its limits, and the autotuner (which tries it on
 small batches and requires equal results)."""
@@ -89,6 +90,35 @@ def test_wide_large_blocks():
         _oracle_check(qm, ref.pruned_search(qs, k, cut, hf, c_cap=cut), k, cut)
         for threads, depth in ((256, 1), (512, 2), (256, 64)):
             assert _same(_search(ix, qs, k, cut, hf, 2, window=depth, threads=threads), qm), (threads, depth)
+
+
+def test_wide_item_capacity():
+    # a one-query workspace holds 8192 evaluation items; every document holds
+    # the query's 32 terms, so each of its 32 cut lists has ~64 blocks and at
+    # least 70000 / 256 = 274 chunks: the later lists find the capacity used
+    # up, speculate fewer blocks (reserved items become no-ops) and the
+    # traversal gathers the rest itself (blocks larger than a workgroup too)
+    n, shared, noise = 70_000, 32, 1000
+    rng = np.random.default_rng(31)
+    terms = np.empty((n, shared + 1), dtype=np.uint32)
+    terms[:, :shared] = np.arange(shared, dtype=np.uint32)
+    terms[:, shared] = shared + rng.integers(0, noise, n)
+    vals = np.clip(rng.lognormal(0.0, 0.6, (n, shared + 1)), 0.02, 40.0).astype(np.float16)
+    words = (terms | (vals.view(np.uint16).astype(np.uint32) << 16)).reshape(-1)
+    rp = np.arange(0, n * (shared + 1) + 1, shared + 1, dtype=np.uint64)
+    docs = synth.CSR(rp, words, shared + noise)
+    _log("[wide] 70k documents sharing 32 terms (lambda 70000, beta 64)")
+    ix = Index.build(docs, lam=n, beta=64, gamma=0.4, seed=31)
+    ref = oracle.Index(ix.serialize())
+    ix.upload(0, block_rows=True)
+    q = synth.make_csr([{t: float(v) for t, v in zip(range(shared), rng.uniform(0.5, 3.0, shared))}],
+                       dim=docs.dim)
+    for hf, k in ((0.8, 10), (float("inf"), 10), (0.6, 64)):
+        _log(f"[wide] item capacity: hf={hf} k={k}")
+        qm = _search(ix, q, k, 32, hf, 0)
+        _oracle_check(qm, ref.pruned_search(q, k, 32, hf, c_cap=32), k, 32)
+        for threads in (512, 256):
+            assert _same(_search(ix, q, k, 32, hf, 2, window=64, threads=threads), qm), threads
 
 
 def test_wide_edge_queries(env):
