@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kBT) void k_build_terms(BuildArgs a) {
                 run += tot;
             }
             if (run > a.s_ecap) {
-                // the host discards this build; keep the later steps in bounds
+                // the host discards this index build; keep the later steps in bounds
                 if (tid == 0) atomicOr(a.flags, 8u);
                 for (uint32_t i = tid; i < n; i += kBT) assign[i] = 0;
             } else {
