@@ -359,6 +359,26 @@ __device__ inline void fold_slot_sparse(const SearchLds<NT>& L, TopK<NT>& top, u
     top.merge(nc);
 }
 
+// fold_slot_sparse for window slots [0, m) at once.
+template <int NT>
+__device__ inline void fold_prefix_sparse(const SearchLds<NT>& L, TopK<NT>& top, uint32_t tot, uint32_t m) {
+    const int tid = threadIdx.x;
+    bool cand = false;
+    float sc = 0.0f;
+    uint32_t d = 0;
+    if ((uint32_t)tid < tot && L.cslot[tid] < m) {
+        sc = (float)L.cacc[tid];
+        d = L.cdoc[tid];
+        cand = top.admits(sc, d);
+    }
+    if (!__syncthreads_or(cand ? 1 : 0)) return;
+    uint32_t nc;
+    const uint32_t at = block_exscan<NT>(cand ? 1u : 0u, L.scratch, &nc);
+    if (cand) { top.cs[at] = sc; top.cid[at] = d; }
+    __syncthreads();
+    top.merge(nc);
+}
+
 // Learned-probe decision for one block.  Kept out of line (the search's
 // register budget is set by its gather phase); the parameter pointer is
 // made wave-uniform and read through the constant address space, so the
@@ -712,6 +732,40 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
             __syncthreads();
             gather_and_score<NT, Look>(ix, L, look, tot, nwb, 0);
             wdocs = tot;
+            }
+            if constexpr (WIDE) {
+                if (spec && !learned && !top.full()) {
+                    // Blocks folded before the top-k fills are not tested: fold
+                    // them at once.  While it is not full every positive id
+                    // not yet held enters, and a block's chunk sets hold all
+                    // its positive documents or at least k, so counting their
+                    // new ids finds the first block tested, f, exactly.
+                    uint32_t* cnt = L.wp0;  // free once the candidates are loaded
+                    if ((uint32_t)tid < kMaxW) cnt[tid] = 0;
+                    __syncthreads();
+                    if ((uint32_t)tid < tot) {
+                        const float sc = (float)L.cacc[tid];
+                        const uint32_t d = L.cdoc[tid];
+                        bool fresh = sc > 0.0f;
+                        if (fresh && top.hn > 0) {
+                            const uint32_t r = top.rank_in_heap(sc, d);
+                            fresh = !(r < top.hn && top.hs()[r] == sc && top.hid()[r] == d);
+                        }
+                        if (fresh) atomicAdd(&cnt[L.cslot[tid]], 1u);
+                    }
+                    __syncthreads();
+                    uint32_t run = top.hn, f = 0;
+                    while (f < nwb && run < a.k) run += cnt[f++];
+                    fold_prefix_sparse<NT>(L, top, tot, f);
+                    evaluated += f;
+                    for (uint32_t s = 0; s < f; ++s) {
+                        C.docs += L.wlen[s];
+                        if (tid == 0) C.nnz += L.crs[s];
+                    }
+                    pos += f;  // the rest of the window starts with a full top-k
+                    __syncthreads();
+                    continue;
+                }
             }
             // Whole-window fold.  A probe-owned list makes no decisions.  With
             // the heap_factor rule and a heap already full, fold everything
