@@ -275,6 +275,8 @@ def main():
                     help="search with the alpha_q-MSS query cut of this mass fraction instead of query_cut")
     ap.add_argument("--grid", default="", help="also sweep query_cut x heap_factor, e.g. '5,10,20x0.7,0.8,0.9'")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--lone-only", action="store_true",
+                    help="measure only the lone-query latency (at --hf, default 0.75) and print it as one JSON line")
     ap.add_argument("--knn", type=int, default=20, help="kappa of the kappa-NN graph for the refined form (0 = skip)")
     ap.add_argument("--knn-cut", type=int, default=10, help="query_cut of the graph-building searches")
     ap.add_argument("--knn-hf", type=float, default=0.5, help="heap_factor of the graph-building searches")
@@ -381,6 +383,12 @@ def main():
     out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     out_sc = torch.empty((nq, k), dtype=torch.float32, device=dev)
     cut = 0 if args.query_mass > 0 else W["cut"]
+    if args.lone_only:
+        hf = args.hf if args.hf is not None else 0.75
+        lone = lone_query_latency(binding, ix, q_rp, q_w, qs.dim, nq, k, cut, hf, stream)
+        print(json.dumps({"lone_query_latency": lone, "workload": args.workload, "query_cut": cut, "k": k,
+                          "heap_factor": hf}), flush=True)
+        return
     qmass = args.query_mass
     grid_cuts = sorted({int(c) for c in args.grid.split("x")[0].split(",")}) if args.grid else []
     prefix = torch.zeros((nq, max([cut or binding.MAX_QUERY_NNZ] + grid_cuts)), dtype=torch.int16, device=dev)

@@ -241,7 +241,9 @@ void seismic_workspace_free(seismic_workspace* ws);
    each query's top-k is carried between positions; used when 1 <=
    query_cut <= 64, else query-major), 2 wide (for small batches: one
    workgroup per (query, cut list) scores and sorts the list's summaries;
-   the first `window` blocks (1..64) of every sorted list are cut into
+   the first `window` blocks (1..64; twice as many, at most 64, in batches
+   of at most 4 queries, which leave most of the chip idle) of every
+   sorted list are cut into
    chunks of 256 documents and one workgroup per chunk scores it and keeps
    its k best documents; then one workgroup per query replays Algorithm 2's
    prune decisions in order over those stored sets, gathering any later

@@ -249,7 +249,10 @@ int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64
     if (cfg.blocks_per_cu > 0) per_cu = std::min<int>(per_cu, (int)cfg.blocks_per_cu);
     uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ws->n_cu, nq);
     if (cfg.schedule == 2 && wide_applies(ws, nq, params, nt)) {
-        a.depth = cfg.window;
+        // a batch of at most kWideTinyBatch queries leaves most of the chip
+        // idle: it speculates twice as deep (capped)
+        a.depth_large = cfg.window;
+        a.depth = std::min(2 * cfg.window, seismic_dev::kWideMaxDepth);
         const size_t smem_eval = seismic_dev::search_smem_bytes(256, index->h.dim, index->dev->sort_cap, params->k);
         const int per_cu_eval = seismic_dev::search_blocks_per_cu(256, smem_eval);
         if (per_cu_eval < 1) return fail(SEISMIC_EHIP, "search: kernel does not fit on a CU (%zu bytes of LDS)", smem_eval);

@@ -1129,7 +1129,7 @@ __global__ __launch_bounds__(NT) void k_wide_lists(SearchArgs a) {
                 // the list keeps the longest prefix whose items fit the item
                 // capacity and whose blocks' chunk sets fit one traversal
                 // window (chunks * k <= wd_nt candidates)
-                const uint32_t D0 = min(nb, a.depth);
+                const uint32_t D0 = min(nb, nq <= kWideTinyBatch ? a.depth : a.depth_large);
                 uint32_t b = 0, n = 0, ch = 0;
                 if ((uint32_t)tid < D0) {
                     b = b0 + L.ord[tid];

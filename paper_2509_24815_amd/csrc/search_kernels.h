@@ -60,7 +60,9 @@ struct SearchArgs {
     // decision in order, folding those stored top-k sets for the speculated
     // blocks and gathering the others itself.  Strides: cmax cut lists per
     // query, depth blocks per list.
-    uint32_t depth;         // blocks speculated per cut list (1..kWideMaxDepth)
+    uint32_t depth;         // blocks speculated per cut list in batches of <= kWideTinyBatch queries
+                            // (1..kWideMaxDepth; also the stride of the per-list slots)
+    uint32_t depth_large;   // ... and in larger batches (<= depth)
     uint32_t wd_nt;         // threads of the traversal (its window holds at most wd_nt candidates)
     float* wd_r;            // [nq * cmax * sort_cap] summary scores in (r desc, block asc) order
     uint16_t* wd_ord;       // [nq * cmax * sort_cap] their block index within the list
@@ -82,6 +84,7 @@ constexpr uint32_t kWideMaxCut = 32;    // largest query_cut served by the wide 
 constexpr uint32_t kWideMaxDepth = 64;  // largest speculation depth (blocks per cut list)
 constexpr uint32_t kWideMaxK = 64;      // largest k served by the wide schedule
 constexpr uint32_t kWideChunk = 256;    // documents per evaluation item (= its workgroup size)
+constexpr uint32_t kWideTinyBatch = 4;  // batches this small speculate twice the configured depth
 constexpr uint32_t kWideMetaBytes = 16 * kWideMaxDepth + 32 * kWideMaxCut;  // extra LDS of the wide traversal
 
 // Device buffers of the list-major schedule for up to nq queries.
