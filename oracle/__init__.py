@@ -74,6 +74,8 @@ def _load():
     lib.or_alpha_mss.argtypes = [vp, vp, u64, f64, vp]
     lib.or_alpha_mss.restype = i32
     lib.or_quantize.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), vp]
+    lib.or_summary_scores.argtypes = [vp, vp, u64, ctypes.c_uint32, vp, vp]
+    lib.or_summary_scores.restype = i32
     _lib = lib
     return lib
 
@@ -168,6 +170,24 @@ class Index:
         msg = ctypes.create_string_buffer(512)
         rc = _load().or_check_index(self._h, int(clustering), int(term_stride), msg, 512)
         return "" if rc == 0 else (msg.value.decode() or "check failed")
+
+    def summary_scores(self, terms, halfs, t: int):
+        """Summary scores of term t's list for one query (terms u16/int,
+        halfs fp16): (r [n_blocks] f32 as the pruned search computes them,
+        <q, phi(B_j)> [n_blocks] f32 over the full document vectors)."""
+        terms = np.asarray(terms, dtype=np.uint32)
+        h = np.ascontiguousarray(halfs, dtype=np.float16).view(np.uint16).astype(np.uint32)
+        words = np.ascontiguousarray(terms | (h << 16), dtype=np.uint32)
+        if words.size == 0:
+            words = np.zeros(1, dtype=np.uint32)
+        sec = self.sections()
+        nb = int(sec["list_off"][t + 1]) - int(sec["list_off"][t])
+        r = np.zeros(max(nb, 1), dtype=np.float32)
+        ex = np.zeros(max(nb, 1), dtype=np.float32)
+        rc = _load().or_summary_scores(self._h, _p(words), len(terms), int(t), _p(r), _p(ex))
+        if rc < 0:
+            raise ValueError("term out of range")
+        return r[:nb], ex[:nb]
 
     def pruned_search(self, queries, k: int, cut: int, heap_factor: float, flags: int = 0,
                       nthreads: int = 0, c_cap: int | None = None, probe=None, tau: float = 0.0, knn=None,

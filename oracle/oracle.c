@@ -454,6 +454,33 @@ static float summary_score_exact(const or_index* ix, const double* qd, uint64_t 
 }
 
 /*
+ * Summary scores of one list for one query row (Algorithm 2, the summary
+ * step): out[j] = r_j of the j-th block of term t's list, as the pruned
+ * search computes it (the dequantized gamma-MSS summary of Section 4.1.3),
+ * and, when out_exact is not NULL, out_exact[j] = <q, phi(B_j)> over the
+ * full document vectors.  Returns the number of blocks, or -1 when t is out
+ * of range.
+ */
+int or_summary_scores(const or_index* ix, const uint32_t* q_words, uint64_t q_nnz, uint32_t t,
+                      float* out, float* out_exact) {
+    if (t >= ix->dim) return -1;
+    double* qd = (double*)calloc(ix->dim, sizeof(double));
+    double* phi = (double*)calloc(ix->dim, sizeof(double));
+    uint32_t* touched = (uint32_t*)malloc(sizeof(uint32_t) * ix->dim);
+    for (uint64_t j = 0; j < q_nnz; ++j) {
+        uint32_t qt = w_term(q_words[j]);
+        if (qt < ix->dim) qd[qt] = half_to_double(w_half(q_words[j]));
+    }
+    uint32_t b0 = ix->list_off[t], b1 = ix->list_off[t + 1];
+    for (uint32_t b = b0; b < b1; ++b) {
+        out[b - b0] = summary_score(ix, qd, b);
+        if (out_exact) out_exact[b - b0] = summary_score_exact(ix, qd, b, phi, touched);
+    }
+    free(qd); free(phi); free(touched);
+    return (int)(b1 - b0);
+}
+
+/*
  * Block-pruned search, Algorithm 2 with kappa = 0:
  *   1. cut: the first min(c, n_q) query entries by (value desc, id asc);
  *      c = 0 keeps them all (stand-in for the alpha_q-MSS of the query);

@@ -39,7 +39,7 @@ def write_index(docs, lists, dim, lam=1000, beta=50, gamma=0.4, seed=0) -> bytes
             sum_off.append(len(sterm))
             ms.append(blk["m"])
             ds.append(blk["delta"])
-            cents.append(blk.get("centroid", blk["docs"][0]))
+            cents.append(blk["centroid"] if "centroid" in blk else blk["docs"][0])
         list_off.append(len(ms))
     nb = len(ms)
     head = bytearray(b"SEISMIC\x00")
