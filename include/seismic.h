@@ -319,10 +319,12 @@ int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, cons
  * Exact top-k (Definition "Sparse MIPS") over the index's forward index:
  * the k documents with the largest inner product, ties by id, documents with
  * a zero score excluded, rows padded like seismic_search_batch.  The first
- * call builds a full (untruncated) inverted index on the host and copies it
- * to the device (about 6 bytes per nonzero; synchronous).  queries may be
- * host or device resident (host: copied with a synchronous copy).
- * k <= SEISMIC_MAX_K.
+ * call builds a full (untruncated) inverted index of the resident forward
+ * index on the device (a counting transpose; about 6 bytes per nonzero;
+ * synchronous).  queries may be host or device resident; host queries are
+ * validated (EINVAL) and copied on stream into staging buffers that the
+ * index owns (a call first waits for the previous call's search that read
+ * them).  The search itself is asynchronous on stream.  k <= SEISMIC_MAX_K.
  */
 int exact_topk(const seismic_index* index, const seismic_csr* queries, uint32_t k, uint32_t* out_ids,
                float* out_scores, void* stream);
@@ -431,7 +433,19 @@ int seismic_probe_adam(const float* grad_sum, const float* stats, float* master,
  * out) and delivers results when its event completes; batches on different
  * slots overlap on the device.  Each query's result is exactly what
  * seismic_search_batch gives for it alone (queries are independent).
- * search.probe, when set, must stay valid until the server is freed. */
+ * search.probe, when set, must stay valid until the server is freed.
+ *
+ * Admission by scratch memory: besides a free slot, each admitted query
+ * reserves its device scratch, 4 * nnz + 16 * k + 8 * L * B bytes (words,
+ * result row, top-k state, and block-order buffers for its L = query_cut
+ * (1024 when 0) lists of at most B blocks, B = the index's longest list),
+ * from scratch_bytes; the reservation is returned when its batch completes.
+ * A query whose reservation fails stays first in the queue and is admitted
+ * by a later attempt: it is deferred, never dropped.
+ *
+ * Memory: a request's words are dropped when it is admitted and its result
+ * when the caller releases its ticket (seismic_server_release); a server
+ * that never releases keeps k results per query. */
 typedef struct seismic_server seismic_server;
 typedef struct {
     seismic_search_params search;
@@ -442,6 +456,11 @@ typedef struct {
                                     plus graphs for batches of <= 256 and <= 64 queries in the
                                     workspace's shapes for those sizes */
     seismic_launch_config launch; /* threads = 0: the workspace default */
+    uint64_t scratch_bytes;      /* admission budget (see above); 0 = the slots' capacity alone;
+                                    EINVAL below one query's largest reservation */
+    uint32_t inject_admission_failures; /* host-forced failures for tests: the first n
+                                    reservations fail as if the budget were held */
+    uint32_t reserved;
 } seismic_server_params;
 
 int seismic_server_create(const seismic_index* index, const seismic_server_params* params, seismic_server** out);
@@ -458,17 +477,25 @@ int seismic_server_submit(seismic_server* server, const uint32_t* words, uint32_
 int seismic_server_submit_batch(seismic_server* server, const seismic_csr* queries, const double* not_before,
                                 uint64_t* first_ticket);
 /* Results of tickets [first_ticket, first_ticket + n), all done (ESTATE
- * otherwise): ids/scores [n * k] host, latency [n] seconds; each nullable. */
+ * otherwise) and not released (EINVAL): ids/scores [n * k] host, latency [n]
+ * seconds; each nullable. */
 int seismic_server_results(seismic_server* server, uint64_t first_ticket, uint64_t n, uint32_t* ids, float* scores,
                            double* latency);
 /* 1 and the result (ids/scores [k] host, nullable; latency = completion -
  * max(submission, not_before) in seconds) when done, 0 while pending, < 0 on
  * error (a failed batch stops the server). */
 int seismic_server_poll(seismic_server* server, uint64_t ticket, uint32_t* ids, float* scores, double* latency);
+/* Drop the results of every ticket below end_ticket (later results, polls
+ * and releases of them return EINVAL).  Stops at the first ticket that is not
+ * done (ESTATE); *first_held (nullable) = the first ticket still held. */
+int seismic_server_release(seismic_server* server, uint64_t end_ticket, uint64_t* first_held);
 /* Block until every submitted query is done (ESTATE after timeout_s). */
 int seismic_server_wait_all(seismic_server* server, double timeout_s);
-/* out = submitted, completed, batches launched, most queries in flight. */
-int seismic_server_stats(const seismic_server* server, uint64_t out[4]);
+/* out = submitted, completed, batches launched, most queries in flight,
+ * requests held (queued, in flight, or done and not released), most slots
+ * busy at once, failed scratch reservations (deferred admissions), most
+ * scratch bytes reserved at once. */
+int seismic_server_stats(const seismic_server* server, uint64_t out[8]);
 /* Stops admitting, waits for launched batches, releases everything. */
 void seismic_server_free(seismic_server* server);
 

@@ -59,6 +59,23 @@ static uint64_t half_to_units24(uint16_t h) {
 static inline uint32_t w_term(uint32_t w) { return w & 0xFFFFu; }
 static inline uint16_t w_half(uint32_t w) { return (uint16_t)(w >> 16); }
 
+/* Query rows follow the library's input conventions: at most
+   OR_MAX_QUERY_NNZ entries are read; a row whose terms are not strictly
+   ascending (one entry per coordinate) is answered as an empty query; an
+   entry with a term >= dim or a value that is not finite and positive is
+   ignored. */
+#define OR_MAX_QUERY_NNZ 1024
+
+static uint64_t row_len(uint64_t n) { return n < OR_MAX_QUERY_NNZ ? n : OR_MAX_QUERY_NNZ; }
+
+static int row_ascending(const uint32_t* w, uint64_t n) {
+    for (uint64_t j = 1; j < row_len(n); ++j)
+        if (w_term(w[j]) <= w_term(w[j - 1])) return 0;
+    return 1;
+}
+
+static int value_ok(uint16_t h) { return (h & 0x8000) == 0 && h != 0 && ((h >> 10) & 0x1F) != 31; }
+
 /* ------------------------------------------------------------- index file */
 
 #define OR_MAGIC "SEISMIC"
@@ -261,13 +278,15 @@ int or_exact_topk(const uint64_t* d_ptr, const uint32_t* d_words, uint64_t n_doc
         uint32_t* hid = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)k);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t qi = 0; qi < (int64_t)nq; ++qi) {
-            for (uint64_t j = q_ptr[qi]; j < q_ptr[qi + 1]; ++j) {
+            const int asc = row_ascending(q_words + q_ptr[qi], q_ptr[qi + 1] - q_ptr[qi]);
+            for (uint64_t j = q_ptr[qi]; j < q_ptr[qi] + row_len(q_ptr[qi + 1] - q_ptr[qi]) && asc; ++j) {
                 uint32_t t = w_term(q_words[j]);
                 if (t >= dim) { bad = 1; continue; }
+                if (!value_ok(w_half(q_words[j]))) continue;
                 qd[t] = half_to_double(w_half(q_words[j]));
             }
             int hn = 0;
-            for (uint64_t d = 0; d < n_docs; ++d) {
+            for (uint64_t d = 0; d < n_docs && asc; ++d) {
                 float s = dot_exact(qd, d_words + d_ptr[d], d_ptr[d + 1] - d_ptr[d]);
                 if (s > 0.0f) topk_insert(hs, hid, &hn, k, s, (uint32_t)d);
             }
@@ -467,9 +486,9 @@ int or_summary_scores(const or_index* ix, const uint32_t* q_words, uint64_t q_nn
     double* qd = (double*)calloc(ix->dim, sizeof(double));
     double* phi = (double*)calloc(ix->dim, sizeof(double));
     uint32_t* touched = (uint32_t*)malloc(sizeof(uint32_t) * ix->dim);
-    for (uint64_t j = 0; j < q_nnz; ++j) {
+    for (uint64_t j = 0; j < row_len(q_nnz) && row_ascending(q_words, q_nnz); ++j) {
         uint32_t qt = w_term(q_words[j]);
-        if (qt < ix->dim) qd[qt] = half_to_double(w_half(q_words[j]));
+        if (qt < ix->dim && value_ok(w_half(q_words[j]))) qd[qt] = half_to_double(w_half(q_words[j]));
     }
     uint32_t b0 = ix->list_off[t], b1 = ix->list_off[t + 1];
     for (uint32_t b = b0; b < b1; ++b) {
@@ -545,9 +564,11 @@ int or_pruned_search(const or_index* ix, const uint64_t* q_ptr, const uint32_t* 
             for (int c = 0; c < c_cap; ++c) pref[c] = 0;
             if (out_hmin) for (int c = 0; c < c_cap; ++c) out_hmin[(size_t)qi * c_cap + c] = -1.0f;
             int nqe = 0;
-            for (uint64_t j = q_ptr[qi]; j < q_ptr[qi + 1]; ++j) {
+            const int asc = row_ascending(q_words + q_ptr[qi], q_ptr[qi + 1] - q_ptr[qi]);
+            for (uint64_t j = q_ptr[qi]; j < q_ptr[qi] + row_len(q_ptr[qi + 1] - q_ptr[qi]) && asc; ++j) {
                 uint32_t t = w_term(q_words[j]);
                 if (t >= dim) { bad = 1; continue; }
+                if (!value_ok(w_half(q_words[j]))) continue;
                 qe[nqe].term = t;
                 qe[nqe].h = w_half(q_words[j]);
                 qe[nqe].v = half_to_double(qe[nqe].h);

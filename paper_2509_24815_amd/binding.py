@@ -64,7 +64,9 @@ class LaunchConfig(ctypes.Structure):
 
 class ServerParams(ctypes.Structure):
     _fields_ = [("search", SearchParams), ("max_batch", ctypes.c_uint32), ("n_slots", ctypes.c_uint32),
-                ("max_batch_nnz", ctypes.c_uint32), ("use_graphs", ctypes.c_uint32), ("launch", LaunchConfig)]
+                ("max_batch_nnz", ctypes.c_uint32), ("use_graphs", ctypes.c_uint32), ("launch", LaunchConfig),
+                ("scratch_bytes", ctypes.c_uint64), ("inject_admission_failures", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class TuneResult(ctypes.Structure):
@@ -127,6 +129,7 @@ def load():
         "seismic_server_poll": ([vp, u64, vp, vp, P(ctypes.c_double)], i32),
         "seismic_server_submit_batch": ([vp, P(Csr), vp, P(u64)], i32),
         "seismic_server_results": ([vp, u64, u64, vp, vp, vp], i32),
+        "seismic_server_release": ([vp, u64, P(u64)], i32),
         "seismic_server_wait_all": ([vp, ctypes.c_double], i32),
         "seismic_server_stats": ([vp, vp], i32),
         "seismic_server_free": ([vp], None),
@@ -395,13 +398,14 @@ def seismic_graph_free(graph):
 
 def seismic_server_create(handle, k: int, query_cut: int, heap_factor: float, max_batch: int = 1024,
                           n_slots: int = 4, max_batch_nnz: int = 0, probe=None, probe_tau: float = 0.0,
-                          launch: dict | None = None, use_graphs: bool = True) -> int:
+                          launch: dict | None = None, use_graphs: bool = True, scratch_bytes: int = 0,
+                          inject_admission_failures: int = 0) -> int:
     """probe (device tensor) must outlive the server."""
     sp = _params(k, query_cut, heap_factor, 0, probe, probe_tau)
     lc = LaunchConfig(0, 0, 0, 0) if not launch else LaunchConfig(launch["threads"], launch["blocks_per_cu"],
                                                                   launch["window"], launch.get("schedule", 0))
     p = ServerParams(sp, max_batch, n_slots, max_batch_nnz or max(MAX_QUERY_NNZ, 256 * max_batch),
-                     1 if use_graphs else 0, lc)
+                     1 if use_graphs else 0, lc, int(scratch_bytes), int(inject_admission_failures), 0)
     s = ctypes.c_void_p()
     _check(load().seismic_server_create(handle, ctypes.byref(p), ctypes.byref(s)))
     return s.value
@@ -449,14 +453,23 @@ def seismic_server_poll(server, ticket: int, k: int):
     return None if rc == 0 else (ids, sc, lat.value)
 
 
+def seismic_server_release(server, end_ticket: int) -> int:
+    """Drops the results of tickets below end_ticket; returns the first
+    ticket still held."""
+    b = ctypes.c_uint64()
+    _check(load().seismic_server_release(server, int(end_ticket), ctypes.byref(b)))
+    return b.value
+
+
 def seismic_server_wait_all(server, timeout_s: float = 600.0):
     _check(load().seismic_server_wait_all(server, timeout_s))
 
 
 def seismic_server_stats(server) -> dict:
-    out = np.zeros(4, dtype=np.uint64)
+    out = np.zeros(8, dtype=np.uint64)
     _check(load().seismic_server_stats(server, _ptr(out)))
-    return dict(zip(("submitted", "completed", "batches", "max_inflight"), (int(x) for x in out)))
+    return dict(zip(("submitted", "completed", "batches", "max_inflight", "held", "max_busy_slots",
+                     "deferred_admissions", "peak_scratch_bytes"), (int(x) for x in out)))
 
 
 def seismic_server_free(server):

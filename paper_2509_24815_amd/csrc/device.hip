@@ -24,6 +24,7 @@ void device_index_free(DeviceIndex* d) {
     (void)hipFree(d->csc_val);
     (void)hipFree(d->xq_ptr);
     (void)hipFree(d->xq_words);
+    if (d->xq_done) (void)hipEventDestroy(d->xq_done);
     (void)hipFree(d->knn);
     (void)hipFree(d->term_rank);
     if (switched) (void)hipSetDevice(prev);
@@ -830,13 +831,21 @@ int exact_topk(const seismic_index* index_c, const seismic_csr* queries, uint32_
     }
     const uint64_t* q_ptr = queries->row_ptr;
     const uint32_t* q_words = queries->words;
-    if (!queries->on_device) {
+    const bool staged = !queries->on_device;
+    if (staged) {
         int rc = validate_csr_host(queries, SEISMIC_MAX_QUERY_NNZ, "exact_topk: queries");
-        if (!rc) rc = grow((void**)&d->xq_ptr, d->xq_rows_cap, queries->n_rows + 1, sizeof(uint64_t));
+        if (rc) return rc;
+        // the staging buffers are shared by every call on this index: wait
+        // until the previous search that read them (on any stream) is done
+        // before they are resized or overwritten
+        if (!d->xq_done) HIP_TRY(hipEventCreateWithFlags(&d->xq_done, hipEventDisableTiming));
+        else HIP_TRY(hipEventSynchronize(d->xq_done));
+        rc = grow((void**)&d->xq_ptr, d->xq_rows_cap, queries->n_rows + 1, sizeof(uint64_t));
         if (!rc) rc = grow((void**)&d->xq_words, d->xq_words_cap, std::max<uint64_t>(queries->nnz, 1), sizeof(uint32_t));
         if (rc) return rc;
-        HIP_TRY(hipMemcpy(d->xq_ptr, queries->row_ptr, (queries->n_rows + 1) * 8, hipMemcpyHostToDevice));
-        if (queries->nnz) HIP_TRY(hipMemcpy(d->xq_words, queries->words, queries->nnz * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpyAsync(d->xq_ptr, queries->row_ptr, (queries->n_rows + 1) * 8, hipMemcpyHostToDevice, st));
+        if (queries->nnz)
+            HIP_TRY(hipMemcpyAsync(d->xq_words, queries->words, queries->nnz * 4, hipMemcpyHostToDevice, st));
         q_ptr = d->xq_ptr;
         q_words = d->xq_words;
     }
@@ -853,6 +862,7 @@ int exact_topk(const seismic_index* index_c, const seismic_csr* queries, uint32_
     a.out_ids = out_ids;
     a.out_scores = out_scores;
     HIP_TRY(seismic_dev::launch_exact(a, (uint32_t)queries->n_rows, smem, st));
+    if (staged) HIP_TRY(hipEventRecord(d->xq_done, st));
     return SEISMIC_OK;
 }
 

@@ -25,10 +25,12 @@ struct DeviceIndex {
     uint64_t* csc_off = nullptr;
     uint32_t* csc_doc = nullptr;
     uint16_t* csc_val = nullptr;
-    // staging for host-resident queries of exact search
+    // staging for host-resident queries of exact search; xq_done is recorded
+    // after the last launch that reads them, on that launch's stream
     uint64_t* xq_ptr = nullptr;
     uint32_t* xq_words = nullptr;
     size_t xq_rows_cap = 0, xq_words_cap = 0;
+    hipEvent_t xq_done = nullptr;
     // kappa-NN graph [n_docs * kappa] (optional)
     uint32_t* knn = nullptr;
     uint32_t kappa = 0;

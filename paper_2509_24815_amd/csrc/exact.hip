@@ -84,7 +84,17 @@ __global__ __launch_bounds__(kBlock) void k_exact(ExactArgs a) {
     top.k = a.k;
 
     const uint64_t q1 = min(a.q_ptr[qi + 1], a.q_nnz), q0 = min(a.q_ptr[qi], q1);
-    const uint32_t nt = (uint32_t)min<uint64_t>(q1 - q0, (uint64_t)kMaxQ);
+    uint32_t nt = (uint32_t)min<uint64_t>(q1 - q0, (uint64_t)kMaxQ);
+    // a row whose terms are not strictly ascending is answered as an empty
+    // query, as the search does
+    if (tid == 0) misc[1] = 0;
+    __syncthreads();
+    bool unsorted = false;
+    for (uint32_t j = 1 + tid; j < nt; j += kBlock)
+        unsorted |= (a.q_words[q0 + j] & 0xFFFFu) <= (a.q_words[q0 + j - 1] & 0xFFFFu);
+    if (unsorted) misc[1] = 1;
+    __syncthreads();
+    if (misc[1]) nt = 0;
     for (uint32_t j = tid; j < nt; j += kBlock) {
         const uint32_t w = a.q_words[q0 + j];
         const uint32_t t = w & 0xFFFFu, h = w >> 16;

@@ -867,13 +867,20 @@ __device__ __forceinline__ Ingested ingest_query(const SearchArgs& a, const Sear
         if (keep) {
             const uint64_t bit = 1ull << (t & 63u);
             const uint64_t old = atomicOr((unsigned long long*)&L.bq.bits[t >> 6], (unsigned long long)bit);
-            if (old & bit) { st |= 2u; keep = false; }  // repeated term: first writer wins
+            if (old & bit) st |= 2u;  // repeated term
         }
         L.q_term[j] = keep ? (uint16_t)t : (uint16_t)0xFFFFu;
         L.q_half[j] = (uint16_t)h;
     }
     if (st) atomicOr(&L.misc[0], st);
     __syncthreads();
+    if (L.misc[0] & 2u) {
+        // terms not strictly ascending (unsorted or repeated): the row is
+        // answered as an empty query, whatever order the entries came in;
+        // the bits it set are cleared with the slot table below
+        for (uint32_t j = tid; j < nqe; j += NT) L.q_term[j] = 0xFFFFu;
+        __syncthreads();
+    }
     build_prefix<NT>(L.bq.bits, L.bq.pref, nw, L.scratch);
     uint32_t nvalid_local = 0;
     double mass_local = 0.0;
@@ -883,6 +890,9 @@ __device__ __forceinline__ Ingested ingest_query(const SearchArgs& a, const Sear
         if (v) mass_local += (double)half_bits_to_float(L.q_half[j]);
     }
     if (nvalid_local) atomicAdd(&L.misc[1], nvalid_local);
+    // every fp16 value is a multiple of 2^-24 below 2^16, so partial sums of
+    // at most kMaxQ of them are multiples of 2^-24 below 2^26: exact in
+    // fp64 in any order (the same holds for the "before" sums of the cut)
     if (a.qmass > 0.0 && mass_local != 0.0) atomicAdd((double*)&L.misc[8], mass_local);
     __syncthreads();
     const uint32_t nvalid = __builtin_amdgcn_readfirstlane(L.misc[1]);

@@ -10,7 +10,9 @@
 // capacity.  Batches on different slots overlap on the device.  A
 // dispatcher thread admits batches, launches them (optionally as one HIP
 // graph replay per batch) and delivers finished results; callers submit and
-// poll from any thread.
+// poll from any thread.  Admission also reserves each query's device scratch
+// (query_scratch_bytes) from a budget shared by the slots, when one is set; a
+// query whose reservation fails waits in the queue for the next attempt.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -21,22 +23,13 @@
 #include <vector>
 
 #include "device_internal.h"
+#include "serve_store.h"
 
 using namespace seismic;
 
 namespace {
 
 using Clock = std::chrono::steady_clock;
-
-struct Request {
-    std::vector<uint32_t> words;
-    double not_before = 0.0;  // server clock (s): earliest admission
-    double arrival = 0.0;     // max(submit time, not_before)
-    double done_at = 0.0;
-    bool done = false;
-    std::vector<uint32_t> ids;
-    std::vector<float> scores;
-};
 
 constexpr uint32_t kTinyBatch = 64;    // the workspace's shapes for up to 64 queries (wide schedule by default)
 constexpr uint32_t kSmallBatch = 256;  // and for up to 256 queries
@@ -59,6 +52,7 @@ struct Slot {
     uint32_t* h_ids = nullptr;   // pinned
     float* h_scores = nullptr;   // pinned
     std::vector<uint64_t> tickets;
+    uint64_t reserved = 0;       // scratch bytes of the batch in flight
     bool busy = false;
 };
 
@@ -73,9 +67,11 @@ struct seismic_server {
     std::mutex mu;
     std::condition_variable cv_work;  // new requests or stop
     std::condition_variable cv_done;  // results delivered
-    std::deque<Request> reqs;         // by ticket
-    uint64_t next_admit = 0;          // first ticket not yet admitted
-    uint64_t completed = 0, batches = 0, max_inflight = 0;
+    RequestStore store;
+    ScratchBudget budget{0, 0};
+    uint32_t cut_lists = 0;           // most lists a query can visit
+    uint32_t max_list_blocks = 0;     // blocks of the index's longest list
+    uint64_t batches = 0, max_inflight = 0, max_busy = 0;
     bool stop = false;
     int error = 0;
     std::string error_msg;
@@ -191,14 +187,10 @@ void run(seismic_server* sv) {
                 break;
             }
             const double t = sv->now();
-            for (size_t i = 0; i < s.tickets.size(); ++i) {
-                Request& r = sv->reqs[s.tickets[i]];
-                r.ids.assign(s.h_ids + i * k, s.h_ids + (i + 1) * k);
-                r.scores.assign(s.h_scores + i * k, s.h_scores + (i + 1) * k);
-                r.done_at = t;
-                r.done = true;
-            }
-            sv->completed += s.tickets.size();
+            for (size_t i = 0; i < s.tickets.size(); ++i)
+                sv->store.deliver(s.tickets[i], s.h_ids + i * k, s.h_scores + i * k, k, t);
+            sv->budget.release(s.reserved);
+            s.reserved = 0;
             s.tickets.clear();
             s.busy = false;
             progress = true;
@@ -206,26 +198,31 @@ void run(seismic_server* sv) {
         if (progress) sv->cv_done.notify_all();
         if (sv->stop) break;
         // admit arrived requests into free slots
-        uint64_t inflight = 0;
+        uint64_t inflight = 0, busy = 0;
         for (Slot& s : sv->slots) {
-            if (s.busy) { inflight += s.tickets.size(); continue; }
+            if (s.busy) { inflight += s.tickets.size(); ++busy; continue; }
             const double t = sv->now();
             uint32_t nq = 0;
             uint64_t nnz = 0;
             s.h_ptr[0] = 0;
-            while (sv->next_admit < sv->reqs.size() && nq < sv->p.max_batch) {
-                Request& r = sv->reqs[sv->next_admit];
+            while (sv->store.has_pending() && nq < sv->p.max_batch) {
+                ServeRequest& r = sv->store.pending();
                 if (r.not_before > t) break;
                 if (nnz + r.words.size() > sv->p.max_batch_nnz) break;
+                const uint64_t bytes = query_scratch_bytes((uint32_t)r.words.size(), k, sv->cut_lists,
+                                                           sv->max_list_blocks);
+                if (!sv->budget.reserve(bytes)) break;  // deferred: it stays first in the queue
+                s.reserved += bytes;
                 std::memcpy(s.h_words + nnz, r.words.data(), r.words.size() * 4);
                 nnz += r.words.size();
                 s.h_ptr[++nq] = nnz;
-                s.tickets.push_back(sv->next_admit++);
+                s.tickets.push_back(sv->store.admit());
             }
             if (nq == 0) break;
             s.busy = true;
             ++sv->batches;
             inflight += nq;
+            ++busy;
             lk.unlock();
             int rc = launch(sv, s, nq, nnz);
             lk.lock();
@@ -238,6 +235,7 @@ void run(seismic_server* sv) {
             progress = true;
         }
         if (inflight > sv->max_inflight) sv->max_inflight = inflight;
+        if (busy > sv->max_busy) sv->max_busy = busy;
         if (sv->stop) break;
         if (!progress) {
             // sleep until new work, the next scheduled arrival, or a short
@@ -246,8 +244,8 @@ void run(seismic_server* sv) {
             bool any_busy = false;
             for (Slot& s : sv->slots) any_busy |= s.busy;
             if (!any_busy) {
-                if (sv->next_admit < sv->reqs.size())
-                    wait = std::max(0.0, sv->reqs[sv->next_admit].not_before - sv->now());
+                if (sv->store.has_pending())
+                    wait = std::max(0.0, sv->store.pending().not_before - sv->now());
                 else
                     wait = 0.05;
             }
@@ -278,11 +276,21 @@ int seismic_server_create(const seismic_index* index, const seismic_server_param
     if (p.search.k < 1 || p.search.k > SEISMIC_MAX_K || !(p.search.heap_factor > 0.0f) ||
         (p.search.flags & ~SEISMIC_SEARCH_KNN))
         return fail(SEISMIC_EINVAL, "server: invalid search parameters");
+    const uint32_t cut_lists = p.search.query_cut && p.search.query_cut < SEISMIC_MAX_QUERY_NNZ
+                                   ? p.search.query_cut : SEISMIC_MAX_QUERY_NNZ;
+    const uint32_t mlb = index->h.max_blocks_per_list();
+    const uint64_t one = query_scratch_bytes(SEISMIC_MAX_QUERY_NNZ, p.search.k, cut_lists, mlb);
+    if (p.scratch_bytes && p.scratch_bytes < one)
+        return fail(SEISMIC_EINVAL, "server: scratch_bytes %llu is below one query's %llu bytes",
+                    (unsigned long long)p.scratch_bytes, (unsigned long long)one);
     seismic_server* sv = new (std::nothrow) seismic_server();
     if (!sv) return fail(SEISMIC_ENOMEM, "server: host allocation failed");
     sv->index = index;
     sv->p = p;
     sv->device = index->dev->device;
+    sv->budget = ScratchBudget(p.scratch_bytes, p.inject_admission_failures);
+    sv->cut_lists = cut_lists;
+    sv->max_list_blocks = mlb;
     DeviceGuard g(sv->device);
     sv->slots.resize(p.n_slots);
     for (Slot& s : sv->slots) {
@@ -317,7 +325,7 @@ int seismic_server_submit(seismic_server* sv, const uint32_t* words, uint32_t nn
         if (t >= dim || (j && t <= word_term(words[j - 1])) || !half_positive_finite(word_half(words[j])))
             return fail(SEISMIC_EINVAL, "server_submit: invalid query entry %u", j);
     }
-    Request r;
+    ServeRequest r;
     r.words.assign(words, words + nnz);
     const double t = sv->now();
     r.not_before = not_before;
@@ -325,10 +333,9 @@ int seismic_server_submit(seismic_server* sv, const uint32_t* words, uint32_t nn
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->error) return fail(sv->error, "%s", sv->error_msg.c_str());
     if (sv->stop) return fail(SEISMIC_ESTATE, "server_submit: server is stopping");
-    if (!sv->reqs.empty() && not_before < sv->reqs.back().not_before)
+    if (not_before < sv->store.last_not_before())
         return fail(SEISMIC_EINVAL, "server_submit: not_before must not decrease between submissions");
-    *ticket = sv->reqs.size();
-    sv->reqs.push_back(std::move(r));
+    *ticket = sv->store.submit(std::move(r));
     sv->cv_work.notify_one();
     return SEISMIC_OK;
 }
@@ -343,38 +350,51 @@ int seismic_server_submit_batch(seismic_server* sv, const seismic_csr* queries, 
     const uint64_t n = queries->n_rows;
     for (uint64_t i = 1; i < n && not_before; ++i)
         if (not_before[i] < not_before[i - 1]) return fail(SEISMIC_EINVAL, "server_submit_batch: not_before decreases");
-    std::deque<Request> add;
+    std::vector<ServeRequest> add(n);
     const double t = sv->now();
     for (uint64_t i = 0; i < n; ++i) {
-        Request r;
+        ServeRequest& r = add[i];
         r.words.assign(queries->words + queries->row_ptr[i], queries->words + queries->row_ptr[i + 1]);
         r.not_before = not_before ? not_before[i] : 0.0;
         r.arrival = r.not_before > t ? r.not_before : t;
-        add.push_back(std::move(r));
     }
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->error) return fail(sv->error, "%s", sv->error_msg.c_str());
     if (sv->stop) return fail(SEISMIC_ESTATE, "server_submit_batch: server is stopping");
-    if (n && !sv->reqs.empty() && add.front().not_before < sv->reqs.back().not_before)
+    if (n && add.front().not_before < sv->store.last_not_before())
         return fail(SEISMIC_EINVAL, "server_submit_batch: not_before must not decrease between submissions");
-    *first_ticket = sv->reqs.size();
-    for (Request& r : add) sv->reqs.push_back(std::move(r));
+    *first_ticket = sv->store.end();
+    for (ServeRequest& r : add) sv->store.submit(std::move(r));
     sv->cv_work.notify_one();
     return SEISMIC_OK;
 }
+
+namespace {
+// The request behind a ticket, or an error for a released / unknown one.
+const ServeRequest* lookup(seismic_server* sv, uint64_t ticket, const char* who) {
+    const ServeRequest* r = sv->store.get(ticket);
+    if (!r) {
+        if (ticket < sv->store.base())
+            fail(SEISMIC_EINVAL, "%s: ticket %llu was released", who, (unsigned long long)ticket);
+        else
+            fail(SEISMIC_EINVAL, "%s: unknown ticket %llu", who, (unsigned long long)ticket);
+    }
+    return r;
+}
+}  // namespace
 
 int seismic_server_results(seismic_server* sv, uint64_t first_ticket, uint64_t n, uint32_t* ids, float* scores,
                            double* latency) {
     if (!sv) return fail(SEISMIC_EINVAL, "server_results: null server");
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (first_ticket + n > sv->reqs.size()) return fail(SEISMIC_EINVAL, "server_results: unknown tickets");
     const uint32_t k = sv->p.search.k;
     for (uint64_t i = 0; i < n; ++i) {
-        const Request& r = sv->reqs[first_ticket + i];
-        if (!r.done) return fail(SEISMIC_ESTATE, "server_results: ticket %llu is not done", (unsigned long long)(first_ticket + i));
-        if (ids) std::memcpy(ids + i * k, r.ids.data(), k * 4);
-        if (scores) std::memcpy(scores + i * k, r.scores.data(), k * 4);
-        if (latency) latency[i] = r.done_at - r.arrival;
+        const ServeRequest* r = lookup(sv, first_ticket + i, "server_results");
+        if (!r) return SEISMIC_EINVAL;
+        if (!r->done) return fail(SEISMIC_ESTATE, "server_results: ticket %llu is not done", (unsigned long long)(first_ticket + i));
+        if (ids) std::memcpy(ids + i * k, r->ids.data(), k * 4);
+        if (scores) std::memcpy(scores + i * k, r->scores.data(), k * 4);
+        if (latency) latency[i] = r->done_at - r->arrival;
     }
     return SEISMIC_OK;
 }
@@ -382,39 +402,54 @@ int seismic_server_results(seismic_server* sv, uint64_t first_ticket, uint64_t n
 int seismic_server_poll(seismic_server* sv, uint64_t ticket, uint32_t* ids, float* scores, double* latency) {
     if (!sv) return fail(SEISMIC_EINVAL, "server_poll: null server");
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (ticket >= sv->reqs.size()) return fail(SEISMIC_EINVAL, "server_poll: unknown ticket");
-    const Request& r = sv->reqs[ticket];
-    if (!r.done) {
+    const ServeRequest* r = lookup(sv, ticket, "server_poll");
+    if (!r) return SEISMIC_EINVAL;
+    if (!r->done) {
         if (sv->error) return fail(sv->error, "%s", sv->error_msg.c_str());
         return 0;
     }
     const uint32_t k = sv->p.search.k;
-    if (ids) std::memcpy(ids, r.ids.data(), k * 4);
-    if (scores) std::memcpy(scores, r.scores.data(), k * 4);
-    if (latency) *latency = r.done_at - r.arrival;
+    if (ids) std::memcpy(ids, r->ids.data(), k * 4);
+    if (scores) std::memcpy(scores, r->scores.data(), k * 4);
+    if (latency) *latency = r->done_at - r->arrival;
     return 1;
+}
+
+int seismic_server_release(seismic_server* sv, uint64_t end_ticket, uint64_t* first_held) {
+    if (!sv) return fail(SEISMIC_EINVAL, "server_release: null server");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (end_ticket > sv->store.end()) return fail(SEISMIC_EINVAL, "server_release: unknown tickets");
+    const uint64_t b = sv->store.release(end_ticket);
+    if (first_held) *first_held = b;
+    if (b < end_ticket)
+        return fail(SEISMIC_ESTATE, "server_release: ticket %llu is not done", (unsigned long long)b);
+    return SEISMIC_OK;
 }
 
 int seismic_server_wait_all(seismic_server* sv, double timeout_s) {
     if (!sv) return fail(SEISMIC_EINVAL, "server_wait_all: null server");
     std::unique_lock<std::mutex> lk(sv->mu);
     const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(timeout_s));
-    while (sv->completed < sv->reqs.size() && !sv->error) {
-        if (sv->cv_done.wait_until(lk, until) == std::cv_status::timeout && sv->completed < sv->reqs.size())
+    while (sv->store.completed() < sv->store.end() && !sv->error) {
+        if (sv->cv_done.wait_until(lk, until) == std::cv_status::timeout && sv->store.completed() < sv->store.end())
             return fail(SEISMIC_ESTATE, "server_wait_all: %llu of %llu queries done after %.1f s",
-                        (unsigned long long)sv->completed, (unsigned long long)sv->reqs.size(), timeout_s);
+                        (unsigned long long)sv->store.completed(), (unsigned long long)sv->store.end(), timeout_s);
     }
     if (sv->error) return fail(sv->error, "%s", sv->error_msg.c_str());
     return SEISMIC_OK;
 }
 
-int seismic_server_stats(const seismic_server* sv, uint64_t out[4]) {
+int seismic_server_stats(const seismic_server* sv, uint64_t out[8]) {
     if (!sv || !out) return fail(SEISMIC_EINVAL, "server_stats: null argument");
     std::lock_guard<std::mutex> lk(const_cast<seismic_server*>(sv)->mu);
-    out[0] = sv->reqs.size();
-    out[1] = sv->completed;
+    out[0] = sv->store.end();
+    out[1] = sv->store.completed();
     out[2] = sv->batches;
     out[3] = sv->max_inflight;
+    out[4] = sv->store.held();
+    out[5] = sv->max_busy;
+    out[6] = sv->budget.failed();
+    out[7] = sv->budget.peak();
     return SEISMIC_OK;
 }
 

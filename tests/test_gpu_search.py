@@ -131,6 +131,50 @@ def test_invalid_device_rows_are_flagged_not_read_out_of_bounds(cfg1):
         ix.search(binding.host_csr(rp, words, docs.dim), 10, 10, 0.8)  # host rows are validated
 
 
+def test_rows_not_strictly_ascending_are_empty_queries(cfg1):
+    """One rule for device rows whose terms are not strictly ascending
+    (unsorted, or a term repeated next to itself or further on): search in
+    both schedules and exact search answer them as empty queries with the
+    UNSORTED status, as the oracle does; an entry with a zero value is
+    ignored; valid rows around them are unaffected."""
+    import torch
+    docs, qs, ix, ref = cfg1
+    one = 0x3C00 << 16
+    valid = [int(x) for x in qs.words[int(qs.row_ptr[0]):int(qs.row_ptr[1])]]
+    rows = [valid,
+            [9 | one, 7 | one, 300 | one],                 # unsorted
+            [12 | one, 12 | one, 40 | one],                # repeated next to itself
+            [3 | one, 90 | one, 3 | one, 400 | one],       # repeated further on
+            [11 | (0x0000 << 16), 50 | one, 70 | one],     # a zero value (ignored)
+            list(reversed(valid)),                         # a valid row reversed
+            valid]
+    rp = np.zeros(len(rows) + 1, dtype=np.uint64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    words = np.array([w for r in rows for w in r], dtype=np.uint32)
+    csr = synth.CSR(rp, words, docs.dim)
+    _log("[rows not strictly ascending]")
+    r = ref.pruned_search(csr, 10, 10, 0.8, c_cap=10)
+    e_ids, e_sc = oracle.exact_topk(docs, csr, 10)
+    for sched in (0, 2):  # query-major and wide
+        ws = binding.seismic_workspace_create(ix.handle, 16, 10)
+        try:
+            binding.seismic_workspace_set_config(ws, 256 if sched == 0 else 512, 0, 8 if sched == 0 else 32, sched)
+            ids, sc, pref, cnt = ix.search(to_device_csr(csr), 10, 10, 0.8, stats=True, prefix_stride=10, ws=ws)
+            torch.cuda.synchronize()
+        finally:
+            binding.seismic_workspace_free(ws)
+        st = cnt.cpu().numpy()[:, 6]
+        assert [bool(x & 2) for x in st] == [False, True, True, True, False, True, False]
+        assert st[4] & 8
+        assert np.array_equal(as_u32(ids), r["ids"]) and np.array_equal(sc.cpu().numpy(), r["scores"])
+        assert np.array_equal(pref.cpu().numpy().view(np.uint16), r["prefix"])
+        for q in (1, 2, 3, 5):
+            assert (as_u32(ids)[q] == 0xFFFFFFFF).all()
+    x_ids, x_sc = ix.exact(to_device_csr(csr), 10)
+    assert np.array_equal(as_u32(x_ids), e_ids) and np.array_equal(x_sc.cpu().numpy(), e_sc)
+    assert (e_ids[[1, 2, 3, 5]] == 0xFFFFFFFF).all() and (e_ids[[0, 4, 6]] != 0xFFFFFFFF).any()
+
+
 def test_search_argument_errors(cfg1):
     docs, qs, ix, _ = cfg1
     sub = to_device_csr(qs.subset(range(4)))

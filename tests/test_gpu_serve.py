@@ -52,6 +52,10 @@ def test_served_results_equal_alone_and_oracle(idx, rate, max_batch, slots):
     _log(f"  stats {st}; latency p50 {np.percentile(lat, 50) * 1e3:.3f} ms, p99 {np.percentile(lat, 99) * 1e3:.3f} ms")
     assert st["submitted"] == st["completed"] == qs.n_rows
     assert st["batches"] > 1 and st["max_inflight"] <= slots * max_batch
+    assert st["max_busy_slots"] <= slots
+    if rate >= 100000.0:
+        # arrivals far faster than one batch completes: batches overlapped on the device
+        assert st["max_busy_slots"] >= 2, st
     assert (lat > 0).all()
     r = ref.pruned_search(qs, 10, 10, 0.8, c_cap=10)
     assert np.array_equal(ids, r["ids"]) and np.array_equal(sc, r["scores"])
@@ -105,3 +109,67 @@ def test_server_submit_poll_and_errors(idx):
         binding.seismic_server_free(sv)
     with pytest.raises(SeismicError):
         binding.seismic_server_create(ix.handle, 10, 10, 0.8, max_batch=8, n_slots=0)
+
+
+def _max_reservation(ix, k, cut):
+    """One query's largest scratch reservation (the header's formula)."""
+    return 4 * binding.MAX_QUERY_NNZ + 16 * k + 8 * cut * ix.info()["max_blocks_per_list"]
+
+
+def test_admission_defers_and_never_drops(idx):
+    """Host-forced admission failures and a scratch budget of three queries:
+    queries wait in the queue (deferred) and are all served, in order, with
+    the oracle's results; the reserved scratch never exceeds the budget."""
+    docs, qs, ix, ref = idx
+    n = 200
+    sub = qs.subset(range(n))
+    budget = 3 * _max_reservation(ix, 10, 10)
+    _log(f"[serve] {n} queries, 7 injected admission failures, scratch budget {budget} bytes")
+    sv = binding.seismic_server_create(ix.handle, 10, 10, 0.8, max_batch=64, n_slots=4, scratch_bytes=budget,
+                                       inject_admission_failures=7)
+    try:
+        first = binding.seismic_server_submit_batch(sv, binding.host_csr(sub.row_ptr, sub.words, sub.dim))
+        binding.seismic_server_wait_all(sv, 120.0)
+        ids, sc, lat = binding.seismic_server_results(sv, first, n, 10)
+        st = binding.seismic_server_stats(sv)
+    finally:
+        binding.seismic_server_free(sv)
+    _log(f"  stats {st}")
+    assert st["completed"] == n and st["deferred_admissions"] >= 7
+    assert 0 < st["peak_scratch_bytes"] <= budget
+    # every reservation holds at least the result, top-k and block-order parts
+    least = 16 * 10 + 8 * 10 * ix.info()["max_blocks_per_list"]
+    assert st["max_inflight"] <= budget // least
+    r = ref.pruned_search(sub, 10, 10, 0.8, c_cap=10)
+    assert np.array_equal(ids, r["ids"]) and np.array_equal(sc, r["scores"])
+    with pytest.raises(SeismicError):  # a budget below one query's reservation
+        binding.seismic_server_create(ix.handle, 10, 10, 0.8, max_batch=8, n_slots=1,
+                                      scratch_bytes=_max_reservation(ix, 10, 10) - 1)
+
+
+def test_release_keeps_the_store_bounded(idx):
+    """Waves of queries served and released: the server holds no request
+    after each release, released tickets are refused, later tickets keep
+    counting and their results are still right."""
+    docs, qs, ix, ref = idx
+    sv = binding.seismic_server_create(ix.handle, 10, 10, 0.8, max_batch=64, n_slots=2)
+    try:
+        for wave in range(4):
+            rows = range(wave * 100, wave * 100 + 100)
+            sub = qs.subset(rows)
+            first = binding.seismic_server_submit_batch(sv, binding.host_csr(sub.row_ptr, sub.words, sub.dim))
+            assert first == wave * 100
+            binding.seismic_server_wait_all(sv, 60.0)
+            ids, sc, _ = binding.seismic_server_results(sv, first, 100, 10)
+            r = ref.pruned_search(sub, 10, 10, 0.8, c_cap=10)
+            assert np.array_equal(ids, r["ids"]) and np.array_equal(sc, r["scores"])
+            assert binding.seismic_server_stats(sv)["held"] == 100
+            assert binding.seismic_server_release(sv, first + 100) == first + 100
+            assert binding.seismic_server_stats(sv)["held"] == 0
+            with pytest.raises(SeismicError):
+                binding.seismic_server_poll(sv, first, 10)
+        with pytest.raises(SeismicError):
+            binding.seismic_server_release(sv, 10**6)  # beyond the last ticket
+        assert binding.seismic_server_stats(sv)["completed"] == 400
+    finally:
+        binding.seismic_server_free(sv)
