@@ -155,6 +155,24 @@ def queries(n_queries: int, seed: int = 0, *, law: str = "poisson", stream: int 
     return generate(n_queries, seed=seed, stream=stream, law="uniform", lo=5, hi=200)
 
 
+def wide_values(csr: CSR, seed: int = 0) -> CSR:
+    """The same rows with values redrawn over the whole positive fp16
+    range: per nonzero, with probability 1/2 lognormal(0, 0.6) (unclamped),
+    1/4 log-uniform in [2^-24, 2^-6] (subnormals included) and 1/4
+    log-uniform in [2^6, 65504]; rounded to fp16 (nearest even).  Seeded by
+    (seed, 77) with numpy; the terms are untouched."""
+    rng = np.random.default_rng([seed, 77])
+    n = csr.nnz
+    u = rng.random(n)
+    normal = np.exp(rng.normal(0.0, SIGMA, n))
+    tiny = np.exp2(rng.uniform(-24.0, -6.0, n))
+    huge = np.exp2(rng.uniform(6.0, np.log2(65504.0), n))
+    v = np.where(u < 0.5, normal, np.where(u < 0.75, tiny, huge))
+    h = np.clip(v, 2.0 ** -24, 65504.0).astype(np.float16).view(np.uint16).astype(np.uint32)
+    words = (csr.words & 0xFFFF) | (h << 16)
+    return CSR(csr.row_ptr.copy(), np.ascontiguousarray(words, dtype=np.uint32), csr.dim)
+
+
 def philox4x32_10(ctr, key):
     lib = _load()
     c = (ctypes.c_uint32 * 4)(*ctr)
