@@ -316,6 +316,28 @@ int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, cons
                          const seismic_stats* stats, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search as seismic_search_batch, with the same arguments, outputs and
+ * errors, minus the workspace.  It calls no hipMalloc, hipFree or other
+ * allocating routine: its scratch (the query queue counter, the learned
+ * probe's prepared parameters and the staging of host-resident queries) is
+ * a fixed device array of the library, about 4.3 MB on every device it runs
+ * on, held until the process ends.  The batch always runs the query-major
+ * schedule in a new workspace's shape for its size (results are those of
+ * every schedule).  Limits: host-resident queries at most
+ * SEISMIC_NOALLOC_MAX_ROWS rows and SEISMIC_NOALLOC_MAX_WORDS nonzeros
+ * (EINVAL beyond); device-resident queries have no limit.  Every call on a
+ * device shares that device's array: calls that overlap on one device (two
+ * streams, or two threads) race and must be serialized by the caller.
+ */
+#define SEISMIC_NOALLOC_MAX_ROWS 8192
+#define SEISMIC_NOALLOC_MAX_WORDS (1 << 20)
+int seismic_search_batch_noalloc(const seismic_index* index, const seismic_csr* queries,
+                                 const seismic_search_params* params, uint32_t* out_ids, float* out_scores,
+                                 const seismic_stats* stats, void* stream);
+
+/*
  * Exact top-k (Definition "Sparse MIPS") over the index's forward index:
  * the k documents with the largest inner product, ties by id, documents with
  * a zero score excluded, rows padded like seismic_search_batch.  The first

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libseismic.so")
 OK, EINVAL, ENOMEM, EHIP, EIO, EFORMAT, ESTATE = 0, -1, -2, -3, -4, -5, -6
 MAX_QUERY_NNZ = 1024
 MAX_K = 1024
+NOALLOC_MAX_ROWS = 8192        # host-resident queries of seismic_search_batch_noalloc
+NOALLOC_MAX_WORDS = 1 << 20
 COUNTER_NAMES = ("summary_entries", "blocks_in_lists", "blocks_evaluated", "docs_evaluated",
                  "nnz_evaluated", "prune_tests", "status", "cut_len")
 
@@ -111,6 +113,7 @@ def load():
         "seismic_workspace_get_config": ([vp, u32, P(LaunchConfig)], i32),
         "seismic_autotune": ([vp, vp, P(Csr), P(SearchParams), vp, vp, u32, vp, u32, P(u32), vp], i32),
         "seismic_search_batch": ([vp, vp, P(Csr), P(SearchParams), vp, vp, P(Stats), vp], i32),
+        "seismic_search_batch_noalloc": ([vp, P(Csr), P(SearchParams), vp, vp, P(Stats), vp], i32),
         "exact_topk": ([vp, P(Csr), u32, vp, vp, vp], i32),
         "seismic_probe_collect": ([vp, P(Csr), vp, vp, u32, vp, u32, u32, vp, vp, vp], i32),
         "seismic_probe_trainer_create": ([i32, u32, P(vp)], i32),
@@ -299,6 +302,19 @@ def seismic_search_batch(handle, ws, queries: Csr, k: int, query_cut: int, heap_
     _check(load().seismic_search_batch(handle, ws, ctypes.byref(queries), ctypes.byref(p), _ptr(out_ids),
                                        _ptr(out_scores), ctypes.byref(st) if use_stats else None,
                                        _stream_handle(stream)))
+
+
+def seismic_search_batch_noalloc(handle, queries: Csr, k: int, query_cut: int, heap_factor: float,
+                                 out_ids, out_scores, prefix=None, prefix_stride: int = 0, counters=None,
+                                 stream=None, flags: int = 0, probe=None, probe_tau: float = 0.0,
+                                 list_hmin=None, list_term=None, query_mass: float = 0.0):
+    """seismic_search_batch without a workspace (no device allocation)."""
+    p = _params(k, query_cut, heap_factor, flags, probe, probe_tau, query_mass)
+    st = Stats(_ptr(prefix), prefix_stride, 0, _ptr(counters), _ptr(list_hmin), _ptr(list_term))
+    use_stats = any(x is not None for x in (prefix, counters, list_hmin, list_term))
+    _check(load().seismic_search_batch_noalloc(handle, ctypes.byref(queries), ctypes.byref(p), _ptr(out_ids),
+                                               _ptr(out_scores), ctypes.byref(st) if use_stats else None,
+                                               _stream_handle(stream)))
 
 
 def exact_topk(handle, queries: Csr, k: int, out_ids, out_scores, stream=None):

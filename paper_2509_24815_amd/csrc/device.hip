@@ -867,3 +867,114 @@ int exact_topk(const seismic_index* index_c, const seismic_csr* queries, uint32_
 }
 
 }  // extern "C"
+
+// ------------------------------------------------ search without allocation
+//
+// seismic_search_batch_noalloc: the query-major search with its scratch (the
+// queue counter, the sanitized probe parameters and the staging of
+// host-resident queries) in one file-scope device array instead of a
+// workspace.  Each device holds its own copy of the array; its address is
+// taken once per device with hipGetSymbolAddress, with that device current,
+// and only that address is ever handed to kernels and copies.
+namespace {
+
+constexpr size_t kNaQueueOff = 0;
+constexpr size_t kNaProbeOff = 256;
+constexpr size_t kNaRowsOff = kNaProbeOff + ((seismic_dev::kProbeWords * sizeof(double) + 255) & ~size_t(255));
+constexpr size_t kNaRowsBytes = ((SEISMIC_NOALLOC_MAX_ROWS + 1) * sizeof(uint64_t) + 255) & ~size_t(255);
+constexpr size_t kNaWordsOff = kNaRowsOff + kNaRowsBytes;
+constexpr size_t kNaBytes = kNaWordsOff + (size_t)SEISMIC_NOALLOC_MAX_WORDS * sizeof(uint32_t);
+
+static __device__ __align__(256) uint8_t scratch[kNaBytes];
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+uint8_t* g_na_ptr[kNaMaxDevices] = {};  // device address of scratch, per device
+int g_na_cus[kNaMaxDevices] = {};
+
+// Address of this device's scratch (the device must be current).
+int noalloc_setup(int device, uint8_t** ptr, int* n_cu) {
+    if (device < 0 || device >= kNaMaxDevices) return fail(SEISMIC_EINVAL, "search_noalloc: device %d out of range", device);
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SEISMIC_EHIP, "search_noalloc: hipGetSymbolAddress of the scratch array failed: %s",
+                        hipGetErrorString(e));
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, device));
+        g_na_cus[device] = prop.multiProcessorCount;
+        g_na_ptr[device] = (uint8_t*)p;
+    }
+    *ptr = g_na_ptr[device];
+    *n_cu = g_na_cus[device];
+    return SEISMIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int seismic_search_batch_noalloc(const seismic_index* index, const seismic_csr* queries,
+                                 const seismic_search_params* params, uint32_t* out_ids, float* out_scores,
+                                 const seismic_stats* stats, void* stream) {
+    if (!index || !queries || !params || !out_ids || !out_scores) return fail(SEISMIC_EINVAL, "search_noalloc: null argument");
+    if (!index->dev) return fail(SEISMIC_ESTATE, "search_noalloc: index is not on a device");
+    if (params->k < 1 || params->k > SEISMIC_MAX_K)
+        return fail(SEISMIC_EINVAL, "search_noalloc: k = %u outside [1, %d]", params->k, SEISMIC_MAX_K);
+    if (stats && stats->prefix && stats->prefix_stride < 1) return fail(SEISMIC_EINVAL, "search_noalloc: prefix_stride must be >= 1");
+    if (!queries->on_device && (queries->n_rows > SEISMIC_NOALLOC_MAX_ROWS || queries->nnz > SEISMIC_NOALLOC_MAX_WORDS))
+        return fail(SEISMIC_EINVAL,
+                    "search_noalloc: %llu host queries with %llu nonzeros exceed the scratch (at most %d queries and %d "
+                    "nonzeros; device-resident queries have no limit)",
+                    (unsigned long long)queries->n_rows, (unsigned long long)queries->nnz, SEISMIC_NOALLOC_MAX_ROWS,
+                    SEISMIC_NOALLOC_MAX_WORDS);
+    const int device = index->dev->device;
+    DeviceGuard g(device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "search_noalloc: cannot select device %d", device);
+    uint8_t* ptr = nullptr;
+    int n_cu = 0;
+    int rc = noalloc_setup(device, &ptr, &n_cu);
+    if (rc) return rc;
+    // a workspace view of the scratch: no buffer of its own, no schedule
+    // buffers (so the batch runs query-major), shapes as a new workspace's
+    seismic_workspace ws;
+    ws.index = index;
+    ws.device = device;
+    ws.max_queries = (uint32_t)std::min<uint64_t>(queries->n_rows, 0xFFFFFFFFull);
+    ws.max_k = params->k;
+    ws.n_cu = n_cu;
+    ws.queue = (uint32_t*)(ptr + kNaQueueOff);
+    ws.probe_w = (double*)(ptr + kNaProbeOff);
+    seismic_launch_config cfg{256u, 0, 8u, 0};
+    rc = check_config(&ws, &cfg);
+    if (rc) return rc;
+    if (queries->n_rows <= 256) {
+        const seismic_launch_config wide{512u, 0, 16u, 0};
+        if (check_config(&ws, &wide) == SEISMIC_OK) cfg = wide;
+        clear_error();
+    }
+    for (int b = 0; b < kBuckets; ++b) ws.cfg[b] = cfg;
+    rc = check_params(index, &ws, queries, params);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t* q_ptr = queries->row_ptr;
+    const uint32_t* q_words = queries->words;
+    if (!queries->on_device) {
+        rc = validate_csr_host(queries, SEISMIC_MAX_QUERY_NNZ, "search_noalloc: queries");
+        if (rc) return rc;
+        uint64_t* d_rows = (uint64_t*)(ptr + kNaRowsOff);
+        uint32_t* d_words = (uint32_t*)(ptr + kNaWordsOff);
+        HIP_TRY(hipMemcpyAsync(d_rows, queries->row_ptr, (queries->n_rows + 1) * sizeof(uint64_t),
+                               hipMemcpyHostToDevice, st));
+        if (queries->nnz)
+            HIP_TRY(hipMemcpyAsync(d_words, queries->words, queries->nnz * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        q_ptr = d_rows;
+        q_words = d_words;
+    }
+    return launch_batch(index, &ws, q_ptr, q_words, queries->n_rows, queries->nnz, params, out_ids, out_scores, stats,
+                        cfg, st);
+}
+
+}  // extern "C"
