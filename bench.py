@@ -87,6 +87,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def alg_bytes(counters: np.ndarray, q_nnz: np.ndarray, k: int) -> np.ndarray:
     """Algorithmic HBM bytes per query of one search (layout of the library):
     query row 8 + 4 n_q; per visited list 8 (list offsets); per block of a
@@ -98,36 +110,43 @@ def alg_bytes(counters: np.ndarray, q_nnz: np.ndarray, k: int) -> np.ndarray:
             + 4 * c[:, 4] + 8 * k)
 
 
-def unique_bytes(S: dict, qs, list_term: np.ndarray, prefix: np.ndarray, k: int) -> float:
-    """Compulsory bytes of one batch (layout of the library): what the batch
-    must read at least once, however many of its queries share it -- the
-    queries and results, every summary entry and block header of each
-    distinct visited list, and each distinct evaluated block's posting
-    offsets, postings, row offsets and rows.  The evaluated blocks are
-    recovered from the trace: the i-th visited list of query q evaluated the
-    first prefix[q, i] blocks in the order of Algorithm 2 (summary score
-    desc, block asc); the scores are recomputed from the index exactly (fp64
-    sums of fp16 x grid values, rounded to fp32)."""
+def survey_bytes(counters: np.ndarray, q_nnz: np.ndarray, k: int, distinct_docs=None, distinct_nnz=None) -> np.ndarray:
+    """Algorithmic bytes per query by the hot-path scope's formula: 4 n_q
+    (query) + per block of a visited list 3 per summary entry + 20 (header)
+    + 4 per posting of an evaluated block + per distinct scored document 8
+    (row offset) + 4 per nonzero + 8 k (results).  distinct_docs /
+    distinct_nnz [nq]: the distinct documents of each query's evaluated
+    blocks and their nonzeros; without them every document of an evaluated
+    block is counted (an upper bound)."""
+    c = counters.astype(np.float64)
+    d = c[:, 3] if distinct_docs is None else np.asarray(distinct_docs, np.float64)
+    z = c[:, 4] if distinct_nnz is None else np.asarray(distinct_nnz, np.float64)
+    return 4 * q_nnz + 3 * c[:, 0] + 20 * c[:, 1] + 4 * c[:, 3] + 8 * d + 4 * z + 8 * k
+
+
+def evaluated_blocks(S: dict, qs, list_term: np.ndarray, prefix: np.ndarray):
+    """(query, block) pairs a batch evaluated, recovered from its trace: the
+    i-th visited list of query q evaluated the first prefix[q, i] blocks in
+    the order of Algorithm 2 (summary score desc, block asc); the scores are
+    recomputed from the index exactly (fp64 sums of fp16 x grid values,
+    rounded to fp32)."""
     import scipy.sparse as sp
     nq = qs.n_rows
-    q_nnz = np.diff(qs.row_ptr.astype(np.int64))
-    total = float((8 + 4 * q_nnz).sum() + 8 * k * nq)
     lo = S["list_off"].astype(np.int64)
     so = S["blk_sum_off"].astype(np.int64)
-    po = S["blk_post_off"].astype(np.int64)
     terms = list_term.astype(np.int64)
     valid = list_term != 0xFFFFFFFF
-    ut = np.unique(terms[valid])
-    total += float((8 + 16 * (lo[ut + 1] - lo[ut]) + 3 * (so[lo[ut + 1]] - so[lo[ut]])).sum())
     Q = sp.csr_matrix((qs.values().astype(np.float64), qs.terms(), qs.row_ptr.astype(np.int64)),
                       shape=(nq, qs.dim))
-    evaluated = np.zeros(int(S["n_blocks"]), dtype=bool)
     qi, ci = np.nonzero(valid & (prefix > 0))
     order = np.argsort(terms[qi, ci], kind="stable")
     qi, ci = qi[order], ci[order]
     ts = terms[qi, ci]
     starts = np.concatenate([[0], np.flatnonzero(np.diff(ts)) + 1, [len(ts)]])
+    out_q, out_b = [], []
     for g0, g1 in zip(starts[:-1], starts[1:]):
+        if g1 <= g0:
+            continue
         t = int(ts[g0])
         b0, b1 = int(lo[t]), int(lo[t + 1])
         nb = b1 - b0
@@ -142,14 +161,48 @@ def unique_bytes(S: dict, qs, list_term: np.ndarray, prefix: np.ndarray, k: int)
         ordr = np.argsort(-R, axis=0, kind="stable")  # score desc, block asc on ties
         p = prefix[qi[g0:g1], ci[g0:g1]].astype(np.int64)
         take = np.arange(nb)[:, None] < p[None, :]
-        evaluated[b0 + ordr[take]] = True
-    eb = np.flatnonzero(evaluated)
+        blocks = b0 + ordr  # [nb, group]
+        cols = np.broadcast_to(qi[g0:g1][None, :], blocks.shape)
+        out_b.append(blocks[take])
+        out_q.append(cols[take])
+    if not out_q:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    return np.concatenate(out_q).astype(np.int64), np.concatenate(out_b).astype(np.int64)
+
+
+def trace_bytes(S: dict, qs, list_term: np.ndarray, prefix: np.ndarray, k: int):
+    """(compulsory bytes of the batch, distinct documents [nq], their
+    nonzeros [nq]).  Compulsory: what the batch must read at least once,
+    however many of its queries share it -- the queries and results, every
+    summary entry and block header of each distinct visited list, and each
+    distinct evaluated block's posting offsets, postings, row offsets and
+    rows (layout of the library)."""
+    nq = qs.n_rows
+    q_nnz = np.diff(qs.row_ptr.astype(np.int64))
+    lo = S["list_off"].astype(np.int64)
+    so = S["blk_sum_off"].astype(np.int64)
+    po = S["blk_post_off"].astype(np.int64)
     doc_len = np.diff(S["row_ptr"].astype(np.int64))
+    valid = list_term != 0xFFFFFFFF
+    ut = np.unique(list_term[valid].astype(np.int64))
+    total = float((8 + 4 * q_nnz).sum() + 8 * k * nq)
+    total += float((8 + 16 * (lo[ut + 1] - lo[ut]) + 3 * (so[lo[ut + 1]] - so[lo[ut]])).sum())
+    pq, pb = evaluated_blocks(S, qs, list_term, prefix)
+    eb = np.unique(pb)
     n_docs = po[eb + 1] - po[eb]
     first = np.repeat(po[eb] - np.concatenate([[0], np.cumsum(n_docs)[:-1]]), n_docs)
     posts = S["postings"][np.arange(int(n_docs.sum())) + first]
     total += float(8 * len(eb) + 20 * n_docs.sum() + 4 * doc_len[posts].sum())
-    return total
+    # per query: the distinct documents of its evaluated blocks
+    cnt = po[pb + 1] - po[pb]
+    firsts = np.repeat(po[pb] - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt)
+    docs = S["postings"][np.arange(int(cnt.sum())) + firsts].astype(np.int64)
+    owner = np.repeat(pq, cnt)
+    key = np.unique(owner * int(S["n_docs"]) + docs)
+    kq, kd = key // int(S["n_docs"]), key % int(S["n_docs"])
+    distinct = np.bincount(kq, minlength=nq)
+    distinct_nnz = np.bincount(kq, weights=doc_len[kd].astype(np.float64), minlength=nq)
+    return total, distinct, distinct_nnz
 
 
 def device_collection(torch, synth, n_docs, mean, chunk=2_000_000):
@@ -259,6 +312,8 @@ def main():
     ap.add_argument("--recall", type=float, default=0.95)
     ap.add_argument("--hf", type=float, default=None, help="skip the sweep and use this heap_factor")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget (0 = skip)")
+    ap.add_argument("--cpu-exact-queries", type=int, default=32,
+                    help="queries of the CPU exact brute-force baseline (0 = skip)")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--profile-copy", action="store_true", help="also run a plain copy for counter calibration")
     ap.add_argument("--index-cache", default=None, help="load the index from this file if present, else build and save")
@@ -273,6 +328,9 @@ def main():
                     help="proportional list caps ceil(alpha |L_i|) at build time (0 = fixed lambda)")
     ap.add_argument("--query-mass", type=float, default=0.0,
                     help="search with the alpha_q-MSS query cut of this mass fraction instead of query_cut")
+    ap.add_argument("--cuts", default="",
+                    help="query_cut values of the operating-point search, e.g. '10,15,20,30' (default: the workload's "
+                         "cut for k <= 10, else 10,15,20,30)")
     ap.add_argument("--grid", default="", help="also sweep query_cut x heap_factor, e.g. '5,10,20x0.7,0.8,0.9'")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--lone-only", action="store_true",
@@ -285,8 +343,10 @@ def main():
     ap.add_argument("--no-unique", action="store_true", help="skip the compulsory (unique) bytes of the batch")
     ap.add_argument("--locality", action="store_true",
                     help="also time the batch reordered so that queries sharing their first lists run together")
-    ap.add_argument("--probe", default=os.path.join(ROOT, "paper_2509_24815_amd", "probes", "probe_1m.npy"),
-                    help="learned block-probe weights to evaluate beside the heap_factor rule ('' = skip)")
+    ap.add_argument("--probe", default="train",
+                    help="learned block probe evaluated beside the heap_factor rule: 'train' trains it in this run on "
+                         "the GPU (1M-document index, 500k samples), a path loads saved weights, '' skips it")
+    ap.add_argument("--probe-epochs", type=int, default=200)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -382,7 +442,13 @@ def main():
         args.no_autotune = True
     out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
     out_sc = torch.empty((nq, k), dtype=torch.float32, device=dev)
-    cut = 0 if args.query_mass > 0 else W["cut"]
+    if args.query_mass > 0:
+        cuts = [0]
+    elif args.cuts:
+        cuts = [int(c) for c in args.cuts.split(",")]
+    else:
+        cuts = [W["cut"]] if k <= 10 else [W["cut"], 15, 20, 30]
+    cut = cuts[0]
     if args.lone_only:
         hf = args.hf if args.hf is not None else 0.75
         lone = lone_query_latency(binding, ix, q_rp, q_w, qs.dim, nq, k, cut, hf, stream)
@@ -391,7 +457,8 @@ def main():
         return
     qmass = args.query_mass
     grid_cuts = sorted({int(c) for c in args.grid.split("x")[0].split(",")}) if args.grid else []
-    prefix = torch.zeros((nq, max([cut or binding.MAX_QUERY_NNZ] + grid_cuts)), dtype=torch.int16, device=dev)
+    prefix = torch.zeros((nq, max([c or binding.MAX_QUERY_NNZ for c in cuts] + grid_cuts)), dtype=torch.int16,
+                         device=dev)
     counters = torch.zeros((nq, 8), dtype=torch.int64, device=dev)
 
     # ground truth
@@ -438,7 +505,7 @@ def main():
         rs, rt = recall_of(out_ids.cpu().numpy().view(np.uint32), out_sc.cpu().numpy())
         return dict(recall=round(rs, 4), recall_tie_aware=round(rt, 4), qps=round(nq / dt, 1),
                     docs_evaluated=float(cnt[:, 3].mean()), blocks_evaluated=float(cnt[:, 2].mean()),
-                    alg_gbs=round(float(alg_bytes(cnt, q_nnz, k).sum()) / dt / 1e9, 1))
+                    layout_gbs=round(float(alg_bytes(cnt, q_nnz, k).sum()) / dt / 1e9, 1))
 
     def search_grid(values, key, fn):
         """Walk values from most to least pruning; stop at the first point
@@ -462,23 +529,42 @@ def main():
                 chosen = mid
         return chosen, pts
 
-    # sweep heap_factor (Alg. 2 skip rule r * hf < heap.min: larger hf prunes less)
-    if args.hf:
-        sweep = [dict(hf=args.hf, **measure(args.hf))]
-        log(f"[bench] sweep {sweep[0]}")
-        chosen = args.hf
-    else:
-        chosen, sweep = search_grid(list(W["hfs"]), "hf", measure)
-    if chosen is None:
-        chosen = max(sweep, key=lambda p: p["recall"])["hf"]
-        log(f"[bench] no swept heap_factor reached Recall@10 {args.recall}; using the best ({chosen})")
-    point = next(p for p in sweep if p["hf"] == chosen)
+    # operating point: for each query_cut, sweep heap_factor (Alg. 2 skip rule
+    # r * hf < heap.min: larger hf prunes less) up to the first point that
+    # reaches the recall target; keep the fastest (cut, hf) that does
+    best, cut_points = None, []
+    for c in cuts:
+        cut = c
+        if args.hf:
+            sweep = [dict(hf=args.hf, **measure(args.hf))]
+            log(f"[bench] sweep query_cut {c}: {sweep[0]}")
+            ch = args.hf if sweep[0]["recall"] >= args.recall else None
+        else:
+            ch, sweep = search_grid(list(W["hfs"]), "hf", measure)
+        if ch is not None:
+            pt = next(p for p in sweep if p["hf"] == ch)
+            cut_points.append(dict(query_cut=c, **pt))
+            if best is None or pt["qps"] > best[2]["qps"]:
+                best = (c, ch, pt)
+        else:
+            top = max(sweep, key=lambda p: p["recall"])
+            cut_points.append(dict(query_cut=c, reached_target=False, **top))
+            log(f"[bench] query_cut {c}: no swept heap_factor reached Recall@{k} {args.recall} "
+                f"(best {top['recall']} at hf {top['hf']})")
+    if best is None:
+        c, ch = max(((p["query_cut"], p["hf"], p["recall"]) for p in cut_points), key=lambda x: x[2])[:2]
+        best = (c, ch, next(p for p in cut_points if p["query_cut"] == c))
+        log(f"[bench] no (query_cut, heap_factor) reached Recall@{k} {args.recall}; using the best ({c}, {ch})")
+    cut, chosen, point = best
+    if len(cuts) > 1:
+        log(f"[bench] operating points per query_cut: {cut_points}; chosen query_cut {cut}, heap_factor {chosen}")
 
     # algorithmic bytes of the chosen point
     run(chosen, True)
     torch.cuda.synchronize()
     cnt = counters.cpu().numpy()
-    bytes_per_launch = float(alg_bytes(cnt, q_nnz, k).sum())
+    plain_prefix = prefix.cpu().numpy().view(np.uint16)[:, :max(cut, 1)].copy()
+    layout_bytes = float(alg_bytes(cnt, q_nnz, k).sum())
 
     # launch shape for this batch: the library's autotuner times every shape
     tuned = binding.seismic_workspace_get_config(ws, nq) if args.schedule is not None else None
@@ -507,11 +593,11 @@ def main():
     gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = gpu_ms / args.steps
     qps = nq * args.steps / (gpu_ms / 1e3)
-    achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
     log(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step, {qps:.0f} QPS, wall {wall:.2f} s, "
-        f"{achieved:.1f} GB/s algorithmic")
+        f"{layout_bytes / (ms_per_step / 1e3) / 1e9:.1f} GB/s by the library layout's bytes")
 
     plain_ids = out_ids.cpu().numpy().view(np.uint32).copy()  # results of the timed steps
+    plain_sc = out_sc.cpu().numpy().copy()
 
     locality = None
     if args.locality:
@@ -544,8 +630,10 @@ def main():
                     "vs_batch_order": round(ms_per_step / oms, 4), "same_results": same}
         log(f"[bench] locality order {locality}")
 
-    # compulsory bytes of the batch at the chosen point (lower bound of the traffic)
-    serialized, unique = None, None
+    # the batch's trace at the chosen point: compulsory bytes (lower bound of
+    # the traffic) and each query's distinct scored documents (the scope
+    # formula's row term)
+    serialized, unique, distinct, distinct_nnz = None, None, None, None
     if not on_device and not args.no_unique:
         tu = time.time()
         from paper_2509_24815_amd import indexfile
@@ -553,10 +641,17 @@ def main():
         stride = cut or binding.MAX_QUERY_NNZ
         _, _, pref_t, _, _, term_t = ix.search(qcsr, k, cut, chosen, trace=True, prefix_stride=stride,
                                                query_mass=qmass)
-        unique = unique_bytes(indexfile.sections(serialized), qs, term_t.cpu().numpy().view(np.uint32),
-                              pref_t.cpu().numpy().view(np.uint16), k)
-        log(f"[bench] compulsory bytes of the batch: {unique:.4e} ({unique / bytes_per_launch:.3f} of the "
-            f"algorithmic bytes; {time.time() - tu:.1f} s)")
+        unique, distinct, distinct_nnz = trace_bytes(indexfile.sections(serialized), qs,
+                                                     term_t.cpu().numpy().view(np.uint32),
+                                                     pref_t.cpu().numpy().view(np.uint16), k)
+        log(f"[bench] compulsory bytes of the batch: {unique:.4e} ({unique / layout_bytes:.3f} of the "
+            f"layout's algorithmic bytes); distinct scored documents per query {distinct.mean():.0f} of "
+            f"{cnt[:, 3].mean():.0f} evaluated ({time.time() - tu:.1f} s)")
+    bytes_per_launch = float(survey_bytes(cnt, q_nnz, k, distinct, distinct_nnz).sum())
+    achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
+    log(f"[bench] algorithmic bytes per launch: {bytes_per_launch:.4e} by the scope formula"
+        + ("" if distinct is not None else " (every document of an evaluated block counted)")
+        + f", {layout_bytes:.4e} by the library layout; {achieved:.1f} GB/s")
 
     # query_cut x heap_factor grid (same batch, autotuned shape)
     grid = None
@@ -566,15 +661,29 @@ def main():
         for c in grid_cuts:
             for hf in hf_list:
                 pt = dict(query_cut=c, hf=hf, **measure(hf, c=c))
-                pt["alg_frac"] = round(pt["alg_gbs"] / PEAK_HBM_GBS, 4)
+                pt["layout_frac"] = round(pt["layout_gbs"] / PEAK_HBM_GBS, 4)
                 grid.append(pt)
                 log(f"[bench] grid {pt}")
 
-    # learned block probe (lists that start with a full heap), heap_factor rule elsewhere
-    learned = None
-    if args.probe and os.path.exists(args.probe):
+    # learned block probe (lists that start with a full heap), heap_factor rule
+    # elsewhere: trained here on the GPU by the library's kernels on a
+    # separate 1M-document index and probe-training queries, or loaded
+    learned, probe_src, probe_train = None, None, None
+    if args.probe == "train":
+        from paper_2509_24815_amd import train_probe
+        tt = time.time()
+        weights, probe_train = train_probe.train_probe(epochs=args.probe_epochs, log=log)
+        probe_train = {key: v for key, v in probe_train.items() if key != "loss_history"}
+        probe_train["total_s"] = round(time.time() - tt, 1)
+        probe_src = "trained in this run"
+        log(f"[bench] probe trained: {probe_train}")
+    elif args.probe and os.path.exists(args.probe):
         from paper_2509_24815_amd import probe as P
-        pw = P.to_device(P.load(args.probe), dev)
+        weights = P.load(args.probe)
+        probe_src = os.path.relpath(args.probe, ROOT)
+    if probe_src is not None:
+        from paper_2509_24815_amd import probe as P
+        pw = P.to_device(weights, dev)
         taus = [2.0, 1.5, 1.0, 0.75, 0.5, 0.25, 0.0, -0.25, -0.5, -1.0, -1.5, -2.0, -3.0]
         tau, lpts = search_grid(taus, "tau", lambda t: measure(chosen, pw, t))
         if tau is not None:
@@ -589,14 +698,15 @@ def main():
             l1.record(stream)
             torch.cuda.synchronize()
             lms = l0.elapsed_time(l1) / args.steps
-            learned = {"probe": os.path.relpath(args.probe, ROOT), "tau": tau, "heap_factor_fallback": chosen,
+            learned = {"probe": probe_src, "tau": tau, "heap_factor_fallback": chosen,
                        f"recall_at_{k}": lp["recall"], "qps": round(nq / (lms / 1e3), 1), "ms_per_step": round(lms, 4),
-                       "docs_evaluated": lp["docs_evaluated"], "qps_vs_heap_factor_rule": round(lms and ms_per_step / lms, 4),
+                       "docs_evaluated": round(lp["docs_evaluated"], 1),
+                       "qps_vs_heap_factor_rule": round(lms and ms_per_step / lms, 4),
                        "docs_vs_heap_factor_rule": round(lp["docs_evaluated"] / point["docs_evaluated"], 4),
-                       "sweep": lpts}
+                       "training": probe_train}
         else:
-            learned = {"probe": os.path.relpath(args.probe, ROOT), "reached_target": False, "sweep": lpts}
-        log(f"[bench] learned probe {learned}")
+            learned = {"probe": probe_src, "reached_target": False, "training": probe_train}
+        log(f"[bench] learned probe {learned}; sweep {lpts}")
 
     # refined form: kappa-NN graph built on the GPU with the method itself,
     # then the refinement step after every search
@@ -635,14 +745,16 @@ def main():
                        "query_cut": c, "heap_factor": h, f"recall_at_{k}": best["recall"],
                        "qps": round(nq / (rms / 1e3), 1), "ms_per_step": round(rms, 4),
                        "docs_evaluated": best["docs_evaluated"],
-                       "qps_vs_heap_factor_rule": round(ms_per_step / rms, 4), "sweep": rpts}
+                       "qps_vs_heap_factor_rule": round(ms_per_step / rms, 4)}
         else:
-            refined = {"kappa": args.knn, "graph_build_s": round(knn_s, 1), "reached_target": False, "sweep": rpts}
+            refined = {"kappa": args.knn, "graph_build_s": round(knn_s, 1), "reached_target": False}
+        log(f"[bench] refined sweep {rpts}")
         # both additions together: learned probe for the traversal, then refinement
         if learned and learned.get("tau") is not None:
             taus = [2.0, 1.5, 1.0, 0.75, 0.5, 0.25, 0.0, -0.25, -0.5, -1.0]
             t2, lpts2 = search_grid(taus, "tau", lambda t: measure(chosen, pw, t, flags=binding.SEARCH_KNN))
-            both = {"tau": t2, "heap_factor_fallback": chosen, "sweep": lpts2}
+            both = {"tau": t2, "heap_factor_fallback": chosen}
+            log(f"[bench] learned + refined sweep {lpts2}")
             if t2 is not None:
                 lp2 = next(p_ for p_ in lpts2 if p_["tau"] == t2)
                 for _ in range(args.warmup):
@@ -681,15 +793,28 @@ def main():
             serving[name] = rows
 
     if args.profile_copy:
+        # counter calibration: kernels of known traffic next to the search
+        # in the same profile -- a plain copy (2^28 bytes read and written,
+        # streaming), and a gather of 2^22 random 64-byte rows out of a 4 GiB
+        # table (2^28 bytes read in scattered 64-byte segments, written
+        # contiguously; the 32 MB of row indices are read too)
         n = 1 << 28
         a = torch.empty(n, dtype=torch.uint8, device=dev)
         b = torch.empty(n, dtype=torch.uint8, device=dev)
         for _ in range(3):
             b.copy_(a)
+        del a, b
+        table = torch.zeros((1 << 26, 16), dtype=torch.int32, device=dev)
+        rows = torch.randint(0, 1 << 26, (1 << 22,), dtype=torch.int64, device=dev,
+                             generator=torch.Generator(device=dev).manual_seed(5))
+        for _ in range(3):
+            torch.index_select(table, 0, rows)
         torch.cuda.synchronize()
-        log(f"[bench] copy calibration: 3 copies of {n} bytes")
+        del table, rows
+        log(f"[bench] counter calibration: 3 copies of {n} bytes, 3 gathers of {1 << 22} random 64-byte rows")
 
-    # CPU baseline: the oracle on a bounded sample of the same queries
+    # CPU baseline: the oracle on a bounded sample of the same queries, and
+    # the oracle's exact brute force on a few of them
     cpu = None
     if args.cpu_seconds > 0:
         import oracle
@@ -700,28 +825,66 @@ def main():
         threads = os.cpu_count() or 1
         pilot = qs.subset(range(min(nq, 4 * threads)))
         tp = time.time()
-        ref.pruned_search(pilot, k, cut, chosen, nthreads=threads, c_cap=cut)
+        ref.pruned_search(pilot, k, cut, chosen, nthreads=threads, c_cap=max(cut, 1))
         per_q = (time.time() - tp) / pilot.n_rows
         n_sample = int(max(threads, min(nq, args.cpu_seconds / max(per_q, 1e-9))))
         sample = qs.subset(range(n_sample))
         tc = time.time()
-        r = ref.pruned_search(sample, k, cut, chosen, nthreads=threads, c_cap=cut)
+        r = ref.pruned_search(sample, k, cut, chosen, nthreads=threads, c_cap=max(cut, 1))
         cpu_s = time.time() - tc
-        g_ids = plain_ids[:n_sample]
-        match = float((r["ids"] == g_ids).all(axis=1).mean())
+        # a query matches when its ids, scores and per-list evaluated prefixes all equal the GPU's
+        same = ((r["ids"] == plain_ids[:n_sample]).all(axis=1) & (r["scores"] == plain_sc[:n_sample]).all(axis=1)
+                & (r["prefix"][:, :plain_prefix.shape[1]] == plain_prefix[:n_sample]).all(axis=1))
         # the paper's protocol: one thread, mean latency per query
         one = qs.subset(range(min(nq, max(8, int(3.0 / max(per_q * threads, 1e-9))))))
         t1 = time.time()
-        ref.pruned_search(one, k, cut, chosen, nthreads=1, c_cap=cut)
+        ref.pruned_search(one, k, cut, chosen, nthreads=1, c_cap=max(cut, 1))
         st_ms = (time.time() - t1) / one.n_rows * 1e3
         cpu = {"value": round(n_sample / cpu_s, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": f"first {n_sample} of the {nq} queries, heap_factor {chosen}, {cpu_s:.1f} s",
-               "gpu_match_fraction": match, "single_thread_ms_per_query": round(st_ms, 3),
-               "single_thread_sample": one.n_rows}
+               "gpu_match_fraction": float(same.mean()), "gpu_match": "ids, scores and evaluated prefixes",
+               "single_thread_ms_per_query": round(st_ms, 3), "single_thread_sample": one.n_rows}
+        if docs is not None and args.cpu_exact_queries > 0:
+            # exact search by brute force over every document: the exact-search CPU baseline
+            ne = min(nq, args.cpu_exact_queries)
+            te = time.time()
+            e_ids, e_sc = oracle.exact_topk(docs, qs.subset(range(ne)), k, threads)
+            ex_s_cpu = time.time() - te
+            cpu["exact"] = {"value": round(ne / ex_s_cpu, 2), "unit": "queries/s", "queries": ne,
+                            "seconds": round(ex_s_cpu, 1),
+                            "gpu_exact_match_fraction": float(((e_ids == ex[:ne]).all(axis=1)
+                                                               & (e_sc == ex_s[:ne]).all(axis=1)).mean()),
+                            "gpu_exact_qps": round(nq / exact_s, 1)}
         log(f"[bench] CPU baseline {cpu}")
         del ref, buf
 
     traffic = measured_traffic(args.workload, chosen, k) if not (args.alpha or qmass) else None
+    step_s = ms_per_step / 1e3
+    # one compact line per form of the method measured in this run
+    forms = {"heap_factor_rule": {"qps": round(qps, 1), f"recall_at_{k}": point["recall"], "heap_factor": chosen,
+                                  "ms_per_step": round(ms_per_step, 4),
+                                  "docs_evaluated": round(point["docs_evaluated"], 1)},
+             "launch": tuned}
+    if learned:
+        forms["learned_probe"] = {key: learned.get(key) for key in
+                                  ("qps", f"recall_at_{k}", "tau", "heap_factor_fallback", "docs_evaluated",
+                                   "qps_vs_heap_factor_rule", "probe", "training")}
+    if refined:
+        forms["knn_refined"] = {key: refined.get(key) for key in
+                                ("qps", f"recall_at_{k}", "kappa", "query_cut", "heap_factor", "graph_build_s",
+                                 "qps_vs_heap_factor_rule")}
+        both = refined.get("with_learned_probe")
+        if both:
+            forms["learned_probe_knn_refined"] = {key: both.get(key) for key in
+                                                  ("qps", f"recall_at_{k}", "tau", "qps_vs_heap_factor_rule")}
+    if lone:
+        forms["lone_query"] = {name: {"p50_ms": v["p50_ms"], "p99_ms": v["p99_ms"]}
+                               for name, v in lone.items() if isinstance(v, dict)}
+    if serving:
+        forms["serving"] = {name: [{"offered_qps": r_["offered_qps"], "sustained_qps": r_["sustained_qps"],
+                                    "p50_ms": r_["p50_ms"], "p99_ms": r_["p99_ms"]} for r_ in rows]
+                            for name, rows in serving.items()}
     out = {
         "metric": "QPS at Recall@10>=0.95 (1 GPU, 8.8M docs); p50/p99 query latency",
         "value": round(qps, 1),
@@ -744,20 +907,19 @@ def main():
                    "index_build_s": None if build_s is None else round(build_s, 1),
                    "index_build": "cached" if build_s is None else
                    ("device-resident" if on_device else "host" if args.host_build else "gpu"),
-                   "hbm": hbm,
-                   "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
-                   "sweep": sweep, "learned_probe": learned, "knn_refined": refined, "grid": grid,
-                   "locality_order": locality},
-        "lone_query_latency": lone,
-        "serving": serving,
+                   "hbm": hbm, "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
+                   "grid": grid, "locality_order": locality},
+        "forms": forms,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "traffic_frac": None if traffic is None else round(traffic / (ms_per_step / 1e3) / 1e9
-                                                                           / PEAK_HBM_GBS, 4),
+                     "traffic_frac": None if traffic is None else round(traffic / step_s / 1e9 / PEAK_HBM_GBS, 4),
                      "alg_bytes_per_launch": bytes_per_launch,
+                     "alg_bytes": "scope formula, distinct scored documents" if distinct is not None
+                     else "scope formula, every document of an evaluated block",
+                     "layout_bytes_per_launch": layout_bytes,
+                     "layout_frac": round(layout_bytes / step_s / 1e9 / PEAK_HBM_GBS, 4),
                      "unique_bytes_per_launch": unique,
-                     "unique_frac": None if unique is None else round(unique / (ms_per_step / 1e3) / 1e9
-                                                                      / PEAK_HBM_GBS, 4)},
+                     "unique_frac": None if unique is None else round(unique / step_s / 1e9 / PEAK_HBM_GBS, 4)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

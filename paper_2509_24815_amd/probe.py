@@ -48,8 +48,12 @@ def load(path: str) -> np.ndarray:
     return w
 
 
-def to_device(weights: np.ndarray, device=None):
+def to_device(weights, device=None):
+    """bf16 bit patterns (numpy uint16, or a torch tensor as train() returns
+    it) as an int16 device tensor."""
     import torch
+    if isinstance(weights, torch.Tensor):
+        return weights.to(device or "cuda").view(torch.int16).contiguous()
     return torch.from_numpy(np.ascontiguousarray(weights).view(np.int16).copy()).to(device or "cuda")
 
 
