@@ -275,6 +275,34 @@ def lone_query_latency(binding, ix, q_rp, q_w, dim, n_rows, k, cut, hf, stream, 
     return out
 
 
+def batch_latency(binding, ix, q_rp, q_w, dim, n_rows, k, cut, hf, stream, sizes=(1, 8, 32, 64, 128), n_batches=12):
+    """Device time of small batches in a new workspace's shapes (the wide
+    schedule up to 64 queries, query-major above): for each size, n_batches
+    batches of consecutive queries spread over the batch, each timed with
+    HIP events on the launch stream after a warm-up of the same batch."""
+    import torch
+    out = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for n in sizes:
+        ws = binding.seismic_workspace_create(ix.handle, n, k)
+        try:
+            ids = torch.empty((n, k), dtype=torch.int32, device=q_w.device)
+            sc = torch.empty((n, k), dtype=torch.float32, device=q_w.device)
+            ts = []
+            for s0 in np.linspace(0, n_rows - n, n_batches).astype(np.int64):
+                q = binding.device_csr(q_rp[int(s0):int(s0) + n + 1], q_w, dim)
+                binding.seismic_search_batch(ix.handle, ws, q, k, cut, hf, ids, sc, stream=stream)
+                e0.record(stream)
+                binding.seismic_search_batch(ix.handle, ws, q, k, cut, hf, ids, sc, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            out[str(n)] = {"mean_ms": round(float(np.mean(ts)), 3), "schedule": binding.seismic_workspace_get_config(ws, n)}
+        finally:
+            binding.seismic_workspace_free(ws)
+    return out
+
+
 def serve_run(binding, ix, qs, rate, seconds, k, cut, hf, probe, tau, max_batch=1024, slots=4):
     """Open-loop Poisson arrivals at `rate` queries/s for `seconds` (queries
     cycle through the batch), served by the library's serving loop.
@@ -777,9 +805,12 @@ def main():
     # arrivals, continuous batching over 4 slots
     serving = None
     lone = None
+    small = None
     if not args.no_serve:
         lone = lone_query_latency(binding, ix, q_rp, q_w, qs.dim, nq, k, cut, chosen, stream)
         log(f"[bench] lone-query latency {lone}")
+        small = batch_latency(binding, ix, q_rp, q_w, qs.dim, nq, k, cut, chosen, stream)
+        log(f"[bench] small-batch latency {small}")
         serving = {}
         rates = (5000.0, 20000.0, 50000.0)
         forms = [("heap_factor_rule", None, 0.0)]
@@ -881,6 +912,8 @@ def main():
     if lone:
         forms["lone_query"] = {name: {"p50_ms": v["p50_ms"], "p99_ms": v["p99_ms"]}
                                for name, v in lone.items() if isinstance(v, dict)}
+    if small:
+        forms["batch_ms"] = {n: v["mean_ms"] for n, v in small.items()}
     if serving:
         forms["serving"] = {name: [{"offered_qps": r_["offered_qps"], "sustained_qps": r_["sustained_qps"],
                                     "p50_ms": r_["p50_ms"], "p99_ms": r_["p99_ms"]} for r_ in rows]

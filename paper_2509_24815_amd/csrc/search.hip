@@ -584,11 +584,16 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
         const double hmin0 = full0 ? (double)top.min_score() : 0.0;
         const bool learned = full0 && a.probe_w != nullptr;
         uint32_t nsurv = 0;
+        // the list's posting offsets, loaded once for all its windows into
+        // soff (the summary offsets are dead from here on): block j holds
+        // postings [soff[j], soff[j + 1])
+        if (tid == 0) L.soff[nb] = ix.blk_post_off[b0 + nb];
         for (uint32_t c = 0; c < nb; c += NT) {
             const uint32_t i = c + tid;
             float rv = 0.0f;
             bool keep = false;
             if (i < nb) {
+                L.soff[i] = ix.blk_post_off[b0 + i];
                 uint32_t bi = i;
                 if constexpr (WIDE) {
                     rv = wr[i];
@@ -691,12 +696,12 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
                 __syncthreads();
             } else {
             if ((uint32_t)tid < W && pos + tid < nsurv) {
-                uint32_t b;
-                if constexpr (WIDE) b = b0 + wo[L.ord[pos + tid]];
-                else b = b0 + L.ord[pos + tid];
-                const uint32_t p0 = ix.blk_post_off[b];
+                uint32_t j;
+                if constexpr (WIDE) j = wo[L.ord[pos + tid]];
+                else j = L.ord[pos + tid];
+                const uint32_t p0 = L.soff[j];
                 L.wp0[tid] = p0;
-                L.wlen[tid] = ix.blk_post_off[b + 1] - p0;
+                L.wlen[tid] = L.soff[j + 1] - p0;
             }
             __syncthreads();
             for (uint32_t s = 0; s < W && pos + s < nsurv; ++s) {
@@ -1107,6 +1112,7 @@ __global__ __launch_bounds__(NT) void k_wide_lists(SearchArgs a) {
         if (item >= n_items) break;
         const uint32_t qi = item / a.cmax, ci = item - qi * a.cmax;
         const Ingested in = ingest_query<NT, true>(a, L, qi, nw);
+        if (ci >= in.ncut && tid == 0) a.wd_nspec[(size_t)qi * a.cmax + ci] = 0;  // past the cut: nothing speculated
         if (ci < in.ncut) {
             const uint32_t t = L.cut[ci];
             const uint32_t b0 = ix.list_off[t], nb = ix.list_off[t + 1] - b0;
@@ -1173,6 +1179,7 @@ __global__ __launch_bounds__(NT) void k_wide_lists(SearchArgs a) {
                 a.wd_nspec[(size_t)qi * a.cmax + ci] = 0;
             }
         }
+        if (ci == 0 && tid == 0) a.wd_lb[qi] = 0.0f;  // the evaluation pass may raise it
         restore_region<NT>(a, L, in);
     }
 }
@@ -1195,15 +1202,38 @@ __global__ __launch_bounds__(kWideChunk) void k_wide_eval(SearchArgs a) {
     if (tid == 0) L.qv[0] = 0.0;
     __syncthreads();
     const uint32_t n_items = min(a.wd_cnt[1], a.wd_icap);
+    const uint32_t nq = a.nq_dev ? min(*a.nq_dev, a.nq) : a.nq;
     const uint32_t per_query = a.cmax * a.depth;
     const uint32_t k = a.k;
+    const bool bound = a.probe_w == nullptr;
     uint32_t cur = 0xFFFFFFFFu;
     Ingested in{};
+    // The queue first hands out, for every query, the first chunk of the
+    // first block of its first cut list (queue positions [0, nq)), then every
+    // item in order (an item already handed out first is skipped).  That
+    // block is evaluated with an empty heap, so every later prune decision
+    // of the query sees a heap minimum at least the k-th best score of that
+    // chunk: the query's bound, published once the chunk is scored.  An item
+    // of a later block whose summary score r has r * hf below the bound is
+    // pruned by the traversal before its candidates could be read, so it is
+    // not scored.  A bound read before it is published is 0 (no skip).
     for (;;) {
         if (tid == 0) L.misc[15] = atomicAdd(a.wd_cnt + 2, 1u);
         __syncthreads();
-        const uint32_t item = __builtin_amdgcn_readfirstlane(L.misc[15]);
-        if (item >= n_items) break;
+        const uint32_t ticket = __builtin_amdgcn_readfirstlane(L.misc[15]);
+        if (ticket >= nq + n_items) break;
+        uint32_t item;
+        const bool first = ticket < nq;
+        if (first) {
+            const size_t qc = (size_t)ticket * a.cmax;
+            if (!bound || a.wd_nspec[qc] == 0) {
+                __syncthreads();
+                continue;
+            }
+            item = a.wd_first[qc * a.depth];
+        } else {
+            item = ticket - nq;
+        }
         const uint4 it = a.wd_items[item];
         const uint32_t b = __builtin_amdgcn_readfirstlane(it.x);
         if (b == 0xFFFFFFFFu) {  // a reserved item left unused
@@ -1212,6 +1242,29 @@ __global__ __launch_bounds__(kWideChunk) void k_wide_eval(SearchArgs a) {
         }
         const uint32_t c = __builtin_amdgcn_readfirstlane(it.y), slot = __builtin_amdgcn_readfirstlane(it.z);
         const uint32_t qi = slot / per_query;
+        if (!first && bound) {
+            const uint32_t lp = slot - qi * per_query, ci = lp / a.depth, pos = lp - ci * a.depth;
+            if (ci == 0 && pos == 0 && c == 0) {  // handed out first
+                __syncthreads();
+                continue;
+            }
+            // the bound may be published while the waves of this workgroup
+            // read it: one read, shared through LDS, keeps the decision (and
+            // the barriers after it) the same for every wave
+            if (tid == 0)
+                L.misc[14] = __float_as_uint(__hip_atomic_load(a.wd_lb + qi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            __syncthreads();
+            const float lb = __uint_as_float(L.misc[14]);
+            const float r = a.wd_r[((size_t)qi * a.cmax + ci) * a.sort_cap + pos];
+            if ((ci > 0 || pos > 0) && (double)r * (double)a.hf < (double)lb) {
+                for (uint32_t i = tid; i < k; i += NT) {
+                    a.wd_ps[(size_t)item * k + i] = -INFINITY;
+                    a.wd_pid[(size_t)item * k + i] = 0xFFFFFFFFu;
+                }
+                __syncthreads();
+                continue;
+            }
+        }
         if (qi != cur) {
             if (cur != 0xFFFFFFFFu) restore_region<NT>(a, L, in);
             in = ingest_query<NT, false>(a, L, qi, nw);
@@ -1243,6 +1296,8 @@ __global__ __launch_bounds__(kWideChunk) void k_wide_eval(SearchArgs a) {
             a.wd_ps[(size_t)item * k + i] = have ? top.hs()[i] : -INFINITY;
             a.wd_pid[(size_t)item * k + i] = have ? top.hid()[i] : 0xFFFFFFFFu;
         }
+        if (first && tid == 0 && top.full())
+            __hip_atomic_store(a.wd_lb + qi, top.min_score(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
     }
 }
@@ -1423,6 +1478,7 @@ hipError_t launch_search_wide(SearchArgs a, const WideSched& w, uint32_t nt, uin
     a.wd_nnz = w.nnz;
     a.wd_ps = w.ps;
     a.wd_pid = w.pid;
+    a.wd_lb = w.lb;
     // the traversal's own window for blocks past the speculated ones
     a.window = nt == 512 ? 16u : 8u;
     a.wd_nt = nt;

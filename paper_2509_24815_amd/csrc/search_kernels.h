@@ -75,6 +75,7 @@ struct SearchArgs {
     uint64_t* wd_nnz;       // [nq * cmax * depth] and their nonzeros
     float* wd_ps;           // [wd_icap * k] top-k scores of each item's chunk (-inf padded)
     uint32_t* wd_pid;       // [wd_icap * k] and ids (0xFFFFFFFF padded)
+    float* wd_lb;           // [nq] lower bound of every heap minimum after the query's first block (0: none)
 };
 
 constexpr uint32_t kModeQuery = 0, kModeList = 1, kModeWide = 2;
@@ -117,6 +118,7 @@ struct WideSched {
     uint64_t* nnz = nullptr;
     float* ps = nullptr;
     uint32_t* pid = nullptr;
+    float* lb = nullptr;
     uint32_t cap = 0, sort_cap = 0, k = 0, icap = 0;
 };
 

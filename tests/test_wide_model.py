@@ -8,7 +8,11 @@ a window committed whole when its last block passes against the merged
 minimum, else block by block — gathering later blocks itself.  The
 model's ids, scores, evaluated-prefix lengths and block, document and test
 counters must equal the oracle's for every query: the decomposition itself
-is exact, independent of the kernels that implement it."""
+is exact, independent of the kernels that implement it.  With the heap bound
+(the k-th best score of the first chunk of the first list's first block,
+evaluated with an empty heap), speculated blocks whose summary score times
+heap_factor falls below it are left unscored, and the results still equal
+the oracle's."""
 import numpy as np
 import pytest
 
@@ -68,7 +72,7 @@ def _merge(H, cands, k):
     return pool[:k]
 
 
-def wide_search(m, qrow, k, cut, hf, depth, chunk, nt, max_w, item_cap):
+def wide_search(m, qrow, k, cut, hf, depth, chunk, nt, max_w, item_cap, bound=False, stats=None):
     """One query through the modelled wide schedule; returns ids, scores,
     prefix and (blocks of cut lists, evaluated blocks, documents, tests)."""
     s = m.s
@@ -92,8 +96,28 @@ def wide_search(m, qrow, k, cut, hf, depth, chunk, nt, max_w, item_cap):
             used += ch
             spec += 1
         lists.append((b0, order, r, spec))
+    # bound: the k-th best score of the first chunk of the first list's
+    # first block (0 when it holds fewer than k positive scores); a
+    # speculated block other than that one whose r * hf is below it is not
+    # scored (its candidate sets are empty)
+    lb = 0.0
+    if bound and lists and lists[0][1]:
+        b0, order = lists[0][0], lists[0][1]
+        first = [m.score(q, int(d)) for d in m.docs_of(b0 + order[0])[:chunk]]
+        first = sorted([x for x in first if x > 0], reverse=True)
+        lb = float(first[k - 1]) if len(first) >= k else 0.0
+    skipped = set()
+    for ci, (b0, order, r, spec) in enumerate(lists):
+        for p in range(spec):
+            if (ci > 0 or p > 0) and float(r[p]) * hf < lb:
+                skipped.add(b0 + order[p])
+    if stats is not None:
+        stats["skipped"] = stats.get("skipped", 0) + len(skipped)
+
     # evaluation pass: each speculated block's chunk top-k sets
     def cands_of(b0, j):
+        if b0 + j in skipped:
+            return []
         docs = m.docs_of(b0 + j)
         out = []
         for c0 in range(0, len(docs), chunk):
@@ -197,17 +221,25 @@ def setup():
 @pytest.mark.parametrize("depth,hf,item_cap,nt", [(1, 0.8, 1 << 30, 40), (3, 0.6, 1 << 30, 40),
                                                   (8, 0.9, 1 << 30, 40), (24, 1.5, 1 << 30, 64),
                                                   (8, 0.8, 20, 40), (24, float("inf"), 1 << 30, 64)])
-def test_wide_model_equals_algorithm_2(setup, depth, hf, item_cap, nt):
+# bound: the speculated blocks below the heap-minimum bound of the first
+# list's first chunk are left unscored (8-document chunks, so that the first
+# chunk can hold k documents and the bound is active)
+@pytest.mark.parametrize("bound", [False, True])
+def test_wide_model_equals_algorithm_2(setup, depth, hf, item_cap, nt, bound):
     m, ref, rows = setup
     k, cut = 5, 8
     qs = synth.make_csr(rows, dim=300)
     r = ref.pruned_search(qs, k, cut, hf, c_cap=cut)
+    stats = {}
     for i, row in enumerate(rows):
-        ids, scores, prefix, (blocks, ev, nd, tests) = wide_search(m, row, k, cut, hf, depth, chunk=4, nt=nt,
-                                                                   max_w=32, item_cap=item_cap)
+        ids, scores, prefix, (blocks, ev, nd, tests) = wide_search(m, row, k, cut, hf, depth,
+                                                                   chunk=8 if bound else 4, nt=nt, max_w=32,
+                                                                   item_cap=item_cap, bound=bound, stats=stats)
         assert ids == r["ids"][i].tolist(), i
         assert np.array_equal(scores, r["scores"][i]), i
         n = len(prefix)
         assert prefix == r["prefix"][i][:n].tolist() and not r["prefix"][i][n:].any(), i
         c = r["counters"][i]
         assert (blocks, ev, nd, tests) == (int(c[1]), int(c[2]), int(c[3]), int(c[5])), i
+    if bound and depth > 1 and hf != float("inf"):
+        assert stats["skipped"] > 0  # the bound did leave blocks unscored
