@@ -29,8 +29,11 @@ HF_SWEEP = (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.25, 1.5, 2.0)
 
 WORKLOADS = {
     # name: docs, queries, query law, lambda, beta, gamma, cut, heap factors swept
+    # k100: the (query_cut, heap_factor) reaching Recall@100 0.95 on this
+    # workload (found by the operating-point search with --k 100), timed as a
+    # fixed point beside the k = 10 sweep
     "msmarco-8.8M": dict(n_docs=8_841_823, n_queries=7000, qlaw="uniform", lam=6000, beta=400, gamma=0.4,
-                         cut=10, hfs=HF_SWEEP),
+                         cut=10, hfs=HF_SWEEP, k100=(20, 1.125)),
     "1M": dict(n_docs=1_000_000, n_queries=10_000, qlaw="poisson", lam=3000, beta=150, gamma=0.4,
                cut=10, hfs=HF_SWEEP),
     "100k": dict(n_docs=100_000, n_queries=1000, qlaw="poisson", lam=1000, beta=50, gamma=0.4,
@@ -60,27 +63,26 @@ def kernel_sha() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, hf: float, k: int):
-    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary
-    of this workload and operating point, or None when there is none or the
-    kernel has changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"k_search_{workload}_hbm_traffic.md")
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    with open(path) as f:
-        for line in f:
-            if ":" in line and not line.startswith((" ", "|", "#")):
-                key, val = line.split(":", 1)
-                kv[key.strip()] = val.strip()
-    try:
-        if kv.get("source_sha256") != kernel_sha():
-            return None
-        if kv.get("workload") != f"{workload} heap_factor {hf} k {k}":
-            return None
-        return float(kv["traffic_bytes_per_launch"].split()[0])
-    except (KeyError, ValueError):
-        return None
+def measured_traffic(workload: str, cut: int, hf: float, k: int):
+    """HBM-side bytes per launch from a committed rocprofv3 summary of this
+    workload and operating point (profiles/k_search_<workload>_*traffic.md:
+    request-size-resolved read and write counters), or None when there is
+    none or the kernel has changed since it was taken."""
+    import glob
+    want = f"{workload} query_cut {cut} heap_factor {hf} k {k}"
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"k_search_{workload}_*traffic.md"))):
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and not line.startswith((" ", "|", "#")):
+                    key, val = line.split(":", 1)
+                    kv[key.strip()] = val.strip()
+        try:
+            if kv.get("workload") == want and kv.get("source_sha256") == kernel_sha():
+                return float(kv["traffic_bytes_per_launch"].split()[0])
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def log(msg):
@@ -361,6 +363,7 @@ def main():
                          "cut for k <= 10, else 10,15,20,30)")
     ap.add_argument("--grid", default="", help="also sweep query_cut x heap_factor, e.g. '5,10,20x0.7,0.8,0.9'")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-k100", action="store_true", help="skip the fixed k = 100 operating point")
     ap.add_argument("--lone-only", action="store_true",
                     help="measure only the lone-query latency (at --hf, default 0.75) and print it as one JSON line")
     ap.add_argument("--knn", type=int, default=20, help="kappa of the kappa-NN graph for the refined form (0 = skip)")
@@ -500,9 +503,10 @@ def main():
     ex = ex_ids.cpu().numpy().view(np.uint32)
     ex_s = ex_sc.cpu().numpy()
 
-    def recall_of(ids_np, sc_np):
+    def recall_of(ids_np, sc_np, truth=None):
+        t_ids, t_sc = (ex, ex_s) if truth is None else truth
         strict, tie = [], []
-        for a, b, bs, asc in zip(ids_np, ex, ex_s, sc_np):
+        for a, b, bs, asc in zip(ids_np, t_ids, t_sc, sc_np):
             valid = b != 0xFFFFFFFF
             n = int(valid.sum())
             if n == 0:
@@ -801,6 +805,53 @@ def main():
             refined["with_learned_probe"] = both
         log(f"[bench] refined {refined}")
 
+    # the workload's k = 100 operating point, fixed (no sweep), in the launch
+    # shape its traffic profile was taken in; ground truth: exact top-100
+    k100 = None
+    if W.get("k100") and k == 10 and not (args.no_k100 or args.alpha or qmass):
+        c100, h100 = W["k100"]
+        tx = time.time()
+        t_ids = torch.empty((nq, 100), dtype=torch.int32, device=dev)
+        t_sc = torch.empty((nq, 100), dtype=torch.float32, device=dev)
+        binding.exact_topk(ix.handle, qcsr, 100, t_ids, t_sc, stream)
+        torch.cuda.synchronize()
+        truth = (t_ids.cpu().numpy().view(np.uint32), t_sc.cpu().numpy())
+        log(f"[bench] exact top-100 of {nq} queries on the GPU: {time.time() - tx:.2f} s")
+        o_ids = torch.empty((nq, 100), dtype=torch.int32, device=dev)
+        o_sc = torch.empty((nq, 100), dtype=torch.float32, device=dev)
+        pre = torch.zeros((nq, c100), dtype=torch.int16, device=dev)
+        binding.seismic_workspace_set_config(ws, 256, 3, 8, 0)
+
+        def run100(stats):
+            binding.seismic_search_batch(ix.handle, ws, qcsr, 100, c100, h100, o_ids, o_sc,
+                                         pre if stats else None, c100 if stats else 0,
+                                         counters if stats else None, stream)
+        run100(True)
+        torch.cuda.synchronize()
+        c_np = counters.cpu().numpy()
+        rs, _ = recall_of(o_ids.cpu().numpy().view(np.uint32), o_sc.cpu().numpy(), truth)
+        for _ in range(args.warmup):
+            run100(False)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            run100(False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms100 = e0.elapsed_time(e1) / args.steps
+        lb100 = float(alg_bytes(c_np, q_nnz, 100).sum())
+        tr100 = measured_traffic(args.workload, c100, h100, 100)
+        k100 = {"query_cut": c100, "heap_factor": h100, "recall_at_100": round(rs, 4),
+                "qps": round(nq / (ms100 / 1e3), 1), "ms_per_step": round(ms100, 4),
+                "docs_evaluated": round(float(c_np[:, 3].mean()), 1),
+                "launch": {"threads": 256, "blocks_per_cu": 3, "window": 8, "schedule": 0},
+                "layout_bytes_per_launch": lb100,
+                "layout_frac": round(lb100 / (ms100 / 1e3) / 1e9 / PEAK_HBM_GBS, 4), "traffic": tr100,
+                "traffic_frac": None if tr100 is None else round(tr100 / (ms100 / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+        log(f"[bench] k = 100 point {k100}")
+        del t_ids, t_sc, o_ids, o_sc, pre
+
     # lone-query latency (device time), then the serving loop: Poisson
     # arrivals, continuous batching over 4 slots
     serving = None
@@ -890,7 +941,7 @@ def main():
         log(f"[bench] CPU baseline {cpu}")
         del ref, buf
 
-    traffic = measured_traffic(args.workload, chosen, k) if not (args.alpha or qmass) else None
+    traffic = measured_traffic(args.workload, cut, chosen, k) if not (args.alpha or qmass) else None
     step_s = ms_per_step / 1e3
     # one compact line per form of the method measured in this run
     forms = {"heap_factor_rule": {"qps": round(qps, 1), f"recall_at_{k}": point["recall"], "heap_factor": chosen,
@@ -909,6 +960,8 @@ def main():
         if both:
             forms["learned_probe_knn_refined"] = {key: both.get(key) for key in
                                                   ("qps", f"recall_at_{k}", "tau", "qps_vs_heap_factor_rule")}
+    if k100:
+        forms["k100"] = k100
     if lone:
         forms["lone_query"] = {name: {"p50_ms": v["p50_ms"], "p99_ms": v["p99_ms"]}
                                for name, v in lone.items() if isinstance(v, dict)}
