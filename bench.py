@@ -363,7 +363,8 @@ def main():
                          "cut for k <= 10, else 10,15,20,30)")
     ap.add_argument("--grid", default="", help="also sweep query_cut x heap_factor, e.g. '5,10,20x0.7,0.8,0.9'")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
-    ap.add_argument("--no-k100", action="store_true", help="skip the fixed k = 100 operating point")
+    ap.add_argument("--no-k100", action="store_true",
+                    help="skip the fixed k = 100 operating point (timed only in runs without --hf)")
     ap.add_argument("--lone-only", action="store_true",
                     help="measure only the lone-query latency (at --hf, default 0.75) and print it as one JSON line")
     ap.add_argument("--knn", type=int, default=20, help="kappa of the kappa-NN graph for the refined form (0 = skip)")
@@ -376,7 +377,7 @@ def main():
                     help="also time the batch reordered so that queries sharing their first lists run together")
     ap.add_argument("--probe", default="train",
                     help="learned block probe evaluated beside the heap_factor rule: 'train' trains it in this run on "
-                         "the GPU (1M-document index, 500k samples), a path loads saved weights, '' skips it")
+                         "the GPU (1M-document index, 500k samples), a path loads saved weights, '' or none skips it")
     ap.add_argument("--probe-epochs", type=int, default=200)
     args = ap.parse_args()
 
@@ -709,7 +710,9 @@ def main():
         probe_train["total_s"] = round(time.time() - tt, 1)
         probe_src = "trained in this run"
         log(f"[bench] probe trained: {probe_train}")
-    elif args.probe and os.path.exists(args.probe):
+    elif args.probe not in ("", "none"):
+        if not os.path.exists(args.probe):
+            raise SystemExit(f"--probe {args.probe}: no such file (use 'train', a saved probe, or none)")
         from paper_2509_24815_amd import probe as P
         weights = P.load(args.probe)
         probe_src = os.path.relpath(args.probe, ROOT)
@@ -806,9 +809,10 @@ def main():
         log(f"[bench] refined {refined}")
 
     # the workload's k = 100 operating point, fixed (no sweep), in the launch
-    # shape its traffic profile was taken in; ground truth: exact top-100
+    # shape its traffic profile was taken in; ground truth: exact top-100.
+    # Part of the default run only (not of runs fixing --hf)
     k100 = None
-    if W.get("k100") and k == 10 and not (args.no_k100 or args.alpha or qmass):
+    if W.get("k100") and k == 10 and args.hf is None and not (args.no_k100 or args.alpha or qmass):
         c100, h100 = W["k100"]
         tx = time.time()
         t_ids = torch.empty((nq, 100), dtype=torch.int32, device=dev)

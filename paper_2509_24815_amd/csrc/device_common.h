@@ -130,8 +130,8 @@ struct TopK {
     float* s1;
     uint32_t* i0;
     uint32_t* i1;
-    float* cs;       // [2 * NT]: candidates, then survivors
-    uint32_t* cid;   // [2 * NT]
+    float* cs;       // [NT]: candidates, then the survivors compacted in place
+    uint32_t* cid;   // [NT]
     uint32_t* scratch;  // [NT / 64 + 1]
     uint32_t which;
     uint32_t hn;
@@ -190,10 +190,12 @@ struct TopK {
             const bool dup = pos < hn && hs()[pos] == s && hid()[pos] == d;
             ok = !dup && admits(s, d);
         }
+        // every candidate is in registers before the scan's barriers, so
+        // the survivors overwrite the candidate array
         uint32_t ns;
         const uint32_t at = block_exscan<NT>(ok ? 1u : 0u, scratch, &ns);
-        float* ss = cs + NT;
-        uint32_t* sd = cid + NT;
+        float* ss = cs;
+        uint32_t* sd = cid;
         if (ok) { ss[at] = s; sd[at] = d; }
         __syncthreads();
         if (ns == 0) return 0;

@@ -76,8 +76,8 @@ __global__ __launch_bounds__(kBlock) void k_exact(ExactArgs a) {
     top.s1 = (float*)xbump(p, 4ull * a.k);
     top.i0 = (uint32_t*)xbump(p, 4ull * a.k);
     top.i1 = (uint32_t*)xbump(p, 4ull * a.k);
-    top.cs = (float*)xbump(p, 4ull * 2 * kBlock);
-    top.cid = (uint32_t*)xbump(p, 4ull * 2 * kBlock);
+    top.cs = (float*)xbump(p, 4ull * kBlock);
+    top.cid = (uint32_t*)xbump(p, 4ull * kBlock);
     top.scratch = scratch;
     top.which = 0;
     top.hn = 0;
@@ -218,7 +218,7 @@ size_t exact_smem_bytes(uint32_t k) {
     auto r16 = [](size_t x) { return (x + 15) & ~size_t(15); };
     size_t s = r16(8ull * kRange) + 2 * r16(8ull * kMaxQ) + 2 * r16(4ull * kMaxQ) + r16(4ull * (kMaxQ + 1));
     s += 2 * r16(4ull * kMaxQ) + r16(4ull * (kBlock + 1)) + r16(32);
-    s += 4 * r16(4ull * k) + 2 * r16(4ull * 2 * kBlock);
+    s += 4 * r16(4ull * k) + 2 * r16(4ull * kBlock);
     return s;
 }
 

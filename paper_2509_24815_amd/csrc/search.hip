@@ -127,8 +127,8 @@ __device__ inline uint8_t* carve_lds(uint8_t* base, uint32_t dim, uint32_t P, ui
     top.s1 = (float*)carve(p, 4ull * k);
     top.i0 = (uint32_t*)carve(p, 4ull * k);
     top.i1 = (uint32_t*)carve(p, 4ull * k);
-    top.cs = (float*)carve(p, 4ull * 2 * NT);
-    top.cid = (uint32_t*)carve(p, 4ull * 2 * NT);
+    top.cs = (float*)carve(p, 4ull * NT);
+    top.cid = (uint32_t*)carve(p, 4ull * NT);
     top.scratch = L.scratch;
     top.which = 0;
     top.hn = 0;
@@ -155,7 +155,7 @@ size_t search_smem_bytes_t(uint32_t dim, uint32_t P, uint32_t k) {
     s += r16u(8 * 256) + r16u(2 * kMaxQ);
     s += r16u(4 * ((size_t)P + 1)) + r16u(4 * (size_t)P) + r16u(2 * (size_t)P);
     s += 2 * r16u(4 * kMaxW) + r16u(4 * (kMaxW + 1)) + r16u(4 * (NT / kWave + 8)) + r16u(64);
-    s += 4 * r16u(4 * (size_t)k) + 2 * r16u(4 * 2 * (size_t)NT);
+    s += 4 * r16u(4 * (size_t)k) + 2 * r16u(4 * (size_t)NT);
     s += union_bytes<NT>(P);
     return s;
 }
