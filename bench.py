@@ -611,6 +611,9 @@ def main():
             best_s = min((r for r in res if r[0].get("schedule", 0) == sched), key=lambda r: r[1])
             log(f"[bench]   schedule {sched}: best {best_s[0]} {best_s[1]:.3f} ms")
 
+    if tuned is not None:  # workgroups per CU that actually stay resident in that shape
+        tuned["resident_per_cu"] = binding.seismic_workspace_resident_per_cu(ws, nq, k)
+
     # timed steps
     for _ in range(args.warmup):
         run(chosen, False)
@@ -849,7 +852,8 @@ def main():
         k100 = {"query_cut": c100, "heap_factor": h100, "recall_at_100": round(rs, 4),
                 "qps": round(nq / (ms100 / 1e3), 1), "ms_per_step": round(ms100, 4),
                 "docs_evaluated": round(float(c_np[:, 3].mean()), 1),
-                "launch": {"threads": 256, "blocks_per_cu": 3, "window": 8, "schedule": 0},
+                "launch": {"threads": 256, "blocks_per_cu": 3, "window": 8, "schedule": 0,
+                           "resident_per_cu": binding.seismic_workspace_resident_per_cu(ws, nq, 100)},
                 "layout_bytes_per_launch": lb100,
                 "layout_frac": round(lb100 / (ms100 / 1e3) / 1e9 / PEAK_HBM_GBS, 4), "traffic": tr100,
                 "traffic_frac": None if tr100 is None else round(tr100 / (ms100 / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}

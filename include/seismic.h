@@ -274,6 +274,15 @@ typedef struct {
    used for a batch of n_queries queries. */
 int seismic_workspace_set_config(seismic_workspace* ws, const seismic_launch_config* cfg);
 int seismic_workspace_get_config(const seismic_workspace* ws, uint32_t n_queries, seismic_launch_config* cfg);
+/* Search workgroups per CU that stay resident for a batch of n_queries
+   queries with this k in the workspace's shape for that size: the smaller
+   of the shape's blocks_per_cu (0 = no cap) and what the device fits by LDS
+   and registers, as the persistent grid is sized.  LDS grows with k (16
+   bytes per unit) and with the index's longest list, so a shape asking for
+   3 may hold 2.  Needs the workspace's device.  EINVAL: null argument, k = 0
+   or k > the workspace's max_k. */
+int seismic_workspace_resident_per_cu(const seismic_workspace* ws, uint32_t n_queries, uint32_t k,
+                                      uint32_t* per_cu);
 
 /* One candidate launch shape and its mean time per search_batch call. */
 typedef struct {

@@ -111,6 +111,7 @@ def load():
         "seismic_workspace_free": ([vp], None),
         "seismic_workspace_set_config": ([vp, P(LaunchConfig)], i32),
         "seismic_workspace_get_config": ([vp, u32, P(LaunchConfig)], i32),
+        "seismic_workspace_resident_per_cu": ([vp, u32, u32, P(u32)], i32),
         "seismic_autotune": ([vp, vp, P(Csr), P(SearchParams), vp, vp, u32, vp, u32, P(u32), vp], i32),
         "seismic_search_batch": ([vp, vp, P(Csr), P(SearchParams), vp, vp, P(Stats), vp], i32),
         "seismic_search_batch_noalloc": ([vp, P(Csr), P(SearchParams), vp, vp, P(Stats), vp], i32),
@@ -268,6 +269,13 @@ def seismic_workspace_get_config(ws, n_queries: int) -> dict:
     c = LaunchConfig()
     _check(load().seismic_workspace_get_config(ws, n_queries, ctypes.byref(c)))
     return {"threads": c.threads, "blocks_per_cu": c.blocks_per_cu, "window": c.window, "schedule": c.schedule}
+
+
+def seismic_workspace_resident_per_cu(ws, n_queries: int, k: int) -> int:
+    """Search workgroups per CU that stay resident for such a batch."""
+    n = ctypes.c_uint32()
+    _check(load().seismic_workspace_resident_per_cu(ws, n_queries, k, ctypes.byref(n)))
+    return n.value
 
 
 def _params(k, query_cut, heap_factor, flags=0, probe=None, probe_tau=0.0, query_mass=0.0):

@@ -519,6 +519,22 @@ int seismic_workspace_get_config(const seismic_workspace* ws, uint32_t n_queries
     return SEISMIC_OK;
 }
 
+int seismic_workspace_resident_per_cu(const seismic_workspace* ws, uint32_t n_queries, uint32_t k, uint32_t* per_cu) {
+    if (!ws || !per_cu) return fail(SEISMIC_EINVAL, "resident: null argument");
+    if (k < 1 || k > ws->max_k) return fail(SEISMIC_EINVAL, "resident: k = %u outside [1, %u]", k, ws->max_k);
+    const seismic_launch_config& c = ws->cfg[bucket_of(n_queries)];
+    DeviceGuard g(ws->device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "resident: cannot select device");
+    // the kernel and LDS size the search launches for this shape (the wide
+    // schedule's traversal runs the same instance); the persistent grid is
+    // sized by the same occupancy query
+    const size_t smem = seismic_dev::search_smem_bytes(c.threads, ws->index->h.dim, ws->index->dev->sort_cap, k);
+    int n = seismic_dev::search_blocks_per_cu(c.threads, smem);
+    if (c.blocks_per_cu > 0) n = std::min<int>(n, (int)c.blocks_per_cu);
+    *per_cu = (uint32_t)std::max(n, 0);
+    return SEISMIC_OK;
+}
+
 int seismic_search_batch(const seismic_index* index, seismic_workspace* ws, const seismic_csr* queries,
                          const seismic_search_params* params, uint32_t* out_ids, float* out_scores,
                          const seismic_stats* stats, void* stream) {

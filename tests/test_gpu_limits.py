@@ -97,3 +97,36 @@ def test_list_beyond_the_search_limit_is_refused():
     with pytest.raises(SeismicError) as e:
         ix.upload(0)
     assert e.value.code == binding.EINVAL
+
+
+def test_resident_workgroups_follow_lds():
+    """Workgroups per CU kept resident by the 256-thread search shape on an
+    index whose longest list has 400 blocks (sort capacity 512), as the
+    8.8M benchmark index: three at k = 10 and at k = 100 (the top-k merge
+    compacts its survivors in place, so three 52 KB workgroups fit a CU),
+    fewer at k = 400 (57 KB); results at k = 100 equal the oracle's."""
+    import torch
+    docs = synth.docs(30_000, seed=3)
+    ix = Index.build(docs, lam=2000, beta=400, gamma=0.4, seed=3)
+    assert ix.info()["max_blocks_per_list"] == 400
+    ref = oracle.Index(ix.serialize())
+    torch.cuda.set_device(0)
+    ix.upload(0, block_rows=True)
+    ws = binding.seismic_workspace_create(ix.handle, 256, 400)
+    try:
+        binding.seismic_workspace_set_config(ws, 256, 3, 8, 0)
+        got = {k: binding.seismic_workspace_resident_per_cu(ws, 5000, k) for k in (10, 100, 400)}
+        _log(f"[limits] resident 256-thread workgroups per CU by k: {got}")
+        assert got[10] == 3 and got[100] == 3
+        assert 1 <= got[400] < 3
+        for bad in (0, 401):
+            with pytest.raises(SeismicError):
+                binding.seismic_workspace_resident_per_cu(ws, 5000, bad)
+        qs = synth.queries(200, seed=3, law="uniform")
+        out = ix.search(to_device_csr(qs), 100, 20, 1.125, stats=True, prefix_stride=20, ws=ws)
+        torch.cuda.synchronize()
+        r = ref.pruned_search(qs, 100, 20, 1.125, c_cap=20)
+        assert not compare_with_oracle(out, r, 100, 20)
+    finally:
+        binding.seismic_workspace_free(ws)
+        ix.close()
