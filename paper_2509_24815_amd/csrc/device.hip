@@ -254,8 +254,8 @@ int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64
         // idle: it speculates twice as deep (capped)
         a.depth_large = cfg.window;
         a.depth = std::min(2 * cfg.window, seismic_dev::kWideMaxDepth);
-        const size_t smem_eval = seismic_dev::search_smem_bytes(256, index->h.dim, index->dev->sort_cap, params->k);
-        const int per_cu_eval = seismic_dev::search_blocks_per_cu(256, smem_eval);
+        const size_t smem_eval = seismic_dev::wide_eval_smem_bytes(index->h.dim, params->k);
+        const int per_cu_eval = seismic_dev::wide_eval_blocks_per_cu(smem_eval);
         if (per_cu_eval < 1) return fail(SEISMIC_EHIP, "search: kernel does not fit on a CU (%zu bytes of LDS)", smem_eval);
         const size_t smem_lists = seismic_dev::search_smem_bytes(seismic_dev::kWideListThreads, index->h.dim,
                                                                  index->dev->sort_cap, params->k);

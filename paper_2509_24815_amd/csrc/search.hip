@@ -149,6 +149,68 @@ __device__ inline uint8_t* carve_lds(uint8_t* base, uint32_t dim, uint32_t P, ui
     return u + union_bytes<NT>(P);
 }
 
+// The wide evaluation pass's layout: what one item needs (lookup region,
+// slot values, a one-block window, top-k, ingest and gather scratch) and
+// none of the list traversal's arrays (cut, block offsets, scores, order,
+// summary sums).  The merge candidates live in the row-start array, which
+// is dead once the item's documents are scored, so at k <= kWideMaxK four
+// workgroups fit a CU.
+__device__ inline void carve_lds_eval(uint8_t* base, uint32_t dim, uint32_t k, SearchLds<kWideChunk>& L,
+                                      TopK<kWideChunk>& top) {
+    constexpr int NT = kWideChunk;
+    const uint32_t nw = (dim + 63) / 64;
+    uint8_t* p = base;
+    L.region_bytes = region_bytes_for(dim);
+    L.region = carve(p, L.region_bytes);
+    {
+        uint8_t* b = L.region;
+        L.bq.bits = (uint64_t*)carve(b, 8ull * nw);
+        L.bq.pref = (uint16_t*)carve(b, 2ull * nw);
+        L.bq.val = (float*)carve(b, 4ull * kMaxQ);
+    }
+    L.qv = (double*)carve(p, 8ull * 256);
+    L.cut = nullptr;
+    L.soff = nullptr;
+    L.r = nullptr;
+    L.ord = nullptr;
+    L.wp0 = (uint32_t*)carve(p, 4ull * kMaxW);
+    L.wlen = (uint32_t*)carve(p, 4ull * kMaxW);
+    L.wst = (uint32_t*)carve(p, 4ull * (kMaxW + 1));
+    L.scratch = (uint32_t*)carve(p, 4ull * (NT / kWave + 8));
+    L.misc = (uint32_t*)carve(p, 4ull * 16);
+    top.s0 = (float*)carve(p, 4ull * k);
+    top.s1 = (float*)carve(p, 4ull * k);
+    top.i0 = (uint32_t*)carve(p, 4ull * k);
+    top.i1 = (uint32_t*)carve(p, 4ull * k);
+    top.scratch = L.scratch;
+    top.which = 0;
+    top.hn = 0;
+    top.k = k;
+    uint8_t* u = p;
+    uint8_t* q = u;
+    L.q_term = (uint16_t*)carve(q, 2ull * kMaxQ);
+    L.q_half = (uint16_t*)carve(q, 2ull * kMaxQ);
+    L.A = nullptr;
+    L.B = nullptr;
+    q = u;
+    L.cacc = (double*)carve(q, 8ull * NT);
+    L.crs = (uint64_t*)carve(q, 8ull * NT);
+    L.cdoc = (uint32_t*)carve(q, 4ull * NT);
+    L.clen = (uint32_t*)carve(q, 4ull * NT);
+    L.cslot = (uint8_t*)carve(q, 1ull * NT);
+    top.cs = (float*)L.crs;                  // [NT] floats, then
+    top.cid = (uint32_t*)(top.cs + NT);      // [NT] ids: 8 * NT bytes, as crs
+}
+
+size_t wide_eval_smem_bytes(uint32_t dim, uint32_t k) {
+    constexpr size_t NT = kWideChunk;
+    size_t s = region_bytes_for(dim) + r16u(8 * 256);
+    s += 2 * r16u(4 * kMaxW) + r16u(4 * (kMaxW + 1)) + r16u(4 * (NT / kWave + 8)) + r16u(64);
+    s += 4 * r16u(4 * (size_t)k);
+    const size_t ingest = 2 * 2 * (size_t)kMaxQ + 32, gath = NT * (8 + 8 + 4 + 4 + 1) + 6 * 16;
+    return s + (ingest > gath ? ingest : gath);
+}
+
 template <int NT>
 size_t search_smem_bytes_t(uint32_t dim, uint32_t P, uint32_t k) {
     size_t s = region_bytes_for(dim);
@@ -1197,7 +1259,7 @@ __global__ __launch_bounds__(kWideChunk) void k_wide_eval(SearchArgs a) {
     const uint32_t nw = (ix.dim + 63u) / 64u;
     SearchLds<NT> L;
     TopK<NT> top;
-    carve_lds<NT>(smem, ix.dim, a.sort_cap, a.k, L, top);
+    carve_lds_eval(smem, ix.dim, a.k, L, top);
     for (uint32_t i = tid; i < L.region_bytes / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
     if (tid == 0) L.qv[0] = 0.0;
     __syncthreads();
@@ -1399,6 +1461,11 @@ __global__ __launch_bounds__(256) void k_items_scatter(const uint32_t* nq_dev, u
 size_t search_smem_bytes(uint32_t nt, uint32_t dim, uint32_t sort_cap, uint32_t k) {
     if (nt == 1024) return search_smem_bytes_t<1024>(dim, sort_cap, k);
     return nt == 512 ? search_smem_bytes_t<512>(dim, sort_cap, k) : search_smem_bytes_t<256>(dim, sort_cap, k);
+}
+
+int wide_eval_blocks_per_cu(size_t smem) {
+    int n = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_wide_eval, kWideChunk, smem) == hipSuccess ? n : 0;
 }
 
 int search_blocks_per_cu(uint32_t nt, size_t smem) {

@@ -141,6 +141,9 @@ hipError_t launch_search_wide(SearchArgs a, const WideSched& w, uint32_t nt, uin
                               uint32_t grid_lists, size_t smem_lists, uint32_t grid_eval, size_t smem_eval,
                               hipStream_t stream);
 int search_blocks_per_cu(uint32_t nt, size_t smem);  // resident workgroups per CU (0 on error)
+// The wide evaluation pass's own LDS (k <= kWideMaxK) and residency.
+size_t wide_eval_smem_bytes(uint32_t dim, uint32_t k);
+int wide_eval_blocks_per_cu(size_t smem);
 
 // Exact search over a full inverted index (term -> doc-ascending postings).
 struct ExactArgs {
