@@ -112,7 +112,7 @@ def alg_bytes(counters: np.ndarray, q_nnz: np.ndarray, k: int) -> np.ndarray:
             + 4 * c[:, 4] + 8 * k)
 
 
-def survey_bytes(counters: np.ndarray, q_nnz: np.ndarray, k: int, distinct_docs=None, distinct_nnz=None) -> np.ndarray:
+def scope_bytes(counters: np.ndarray, q_nnz: np.ndarray, k: int, distinct_docs=None, distinct_nnz=None) -> np.ndarray:
     """Algorithmic bytes per query by the hot-path scope's formula: 4 n_q
     (query) + per block of a visited list 3 per summary entry + 20 (header)
     + 4 per posting of an evaluated block + per distinct scored document 8
@@ -683,7 +683,7 @@ def main():
         log(f"[bench] compulsory bytes of the batch: {unique:.4e} ({unique / layout_bytes:.3f} of the "
             f"layout's algorithmic bytes); distinct scored documents per query {distinct.mean():.0f} of "
             f"{cnt[:, 3].mean():.0f} evaluated ({time.time() - tu:.1f} s)")
-    bytes_per_launch = float(survey_bytes(cnt, q_nnz, k, distinct, distinct_nnz).sum())
+    bytes_per_launch = float(scope_bytes(cnt, q_nnz, k, distinct, distinct_nnz).sum())
     achieved = bytes_per_launch / (ms_per_step / 1e3) / 1e9
     log(f"[bench] algorithmic bytes per launch: {bytes_per_launch:.4e} by the scope formula"
         + ("" if distinct is not None else " (every document of an evaluated block counted)")

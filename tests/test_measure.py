@@ -58,7 +58,7 @@ def test_unique_bytes_against_oracle_counters():
         assert distinct_nnz[q] == sum(doc_len[d] for d in seen), q
     assert (distinct <= r["counters"][:, 3]).all() and (distinct < r["counters"][:, 3]).any()
     # the scope formula with distinct documents is below the layout formula
-    sb = bench.survey_bytes(r["counters"], nnz, k, distinct, distinct_nnz)
+    sb = bench.scope_bytes(r["counters"], nnz, k, distinct, distinct_nnz)
     assert (sb < alg).all()
 
 
