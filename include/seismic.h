@@ -267,10 +267,10 @@ typedef struct {
 } seismic_launch_config;
 
 /* A new workspace uses the wide schedule with 512 threads and window 32
-   for batches of up to 64 queries (lowest latency), the query-major
+   for batches of up to 128 queries (lowest latency), the query-major
    schedule with 512 threads and window 16 for up to 256 queries, and 256
    threads and window 8 for larger ones.  set_config applies cfg to every batch-size
-   bucket (<= 64, <= 256, <= 4096, larger); get_config returns the shape
+   bucket (<= 128, <= 256, <= 4096, larger); get_config returns the shape
    used for a batch of n_queries queries. */
 int seismic_workspace_set_config(seismic_workspace* ws, const seismic_launch_config* cfg);
 int seismic_workspace_get_config(const seismic_workspace* ws, uint32_t n_queries, seismic_launch_config* cfg);
@@ -300,7 +300,7 @@ typedef struct {
  * warm-up and `reps` timed calls each (HIP events on `stream`; the call
  * waits for the stream), checks that every shape returns the same ids and
  * scores (EHIP-free mismatch => ESTATE), and stores the fastest shape for
- * the batch-size bucket of queries->n_rows (buckets: <= 64, <= 256, <= 4096,
+ * the batch-size bucket of queries->n_rows (buckets: <= 128, <= 256, <= 4096,
  * larger).  out_ids/out_scores are caller device buffers [n_rows * k] that
  * end up holding the results; results[0..max_results) (nullable) receive
  * every candidate's timing, *n_results their count.  queries must be

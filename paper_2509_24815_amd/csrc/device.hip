@@ -107,7 +107,7 @@ struct seismic_workspace {
 
 namespace {
 
-int bucket_of(uint64_t nq) { return nq <= 64 ? 0 : nq <= 256 ? 1 : nq <= 4096 ? 2 : 3; }
+int bucket_of(uint64_t nq) { return nq <= 128 ? 0 : nq <= 256 ? 1 : nq <= 4096 ? 2 : 3; }
 
 int check_config(const seismic_workspace* ws, const seismic_launch_config* c) {
     if (c->threads != 256 && c->threads != 512) return fail(SEISMIC_EINVAL, "config: threads must be 256 or 512");
@@ -454,12 +454,13 @@ int seismic_workspace_create(const seismic_index* index, uint32_t max_queries, u
     ws->device = index->dev->device;
     ws->max_queries = max_queries;
     ws->max_k = max_k;
-    // default shapes: a batch of up to 64 queries runs the wide schedule
+    // default shapes: a batch of up to 128 queries runs the wide schedule
     // (512-thread list pass and traversal, 32 speculated blocks per list: at
-    // 8.8M, 0.29 ms for one query and 1.0 ms for 32, against 1.7 and 2.1 ms
-    // query-major), up to 256 queries one query per CU with 512-thread
-    // workgroups, larger batches 256-thread workgroups, three per CU; the
-    // autotuner can replace any of them
+    // 8.8M, 0.25 ms for one query, 0.85 ms for 32 and 1.66 ms for 96,
+    // against 1.6, 2.0 and 2.1 ms query-major; even at 128), up to 256
+    // queries one query per CU with 512-thread workgroups, larger batches
+    // 256-thread workgroups, three per CU; the autotuner can replace any of
+    // them
     ws->cfg[0] = seismic_launch_config{512u, 0, 32u, 2u};
     ws->cfg[1] = seismic_launch_config{512u, 0, 16u, 0};
     for (int b = 2; b < kBuckets; ++b) ws->cfg[b] = seismic_launch_config{256u, 0, 8u, 0};

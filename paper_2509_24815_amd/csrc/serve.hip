@@ -31,7 +31,14 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr uint32_t kTinyBatch = 64;    // the workspace's shapes for up to 64 queries (wide schedule by default)
+// Graphs for batches of up to kTinyBatch queries use the wide schedule's
+// shape, larger ones (up to kSmallBatch) query-major: under load, batches
+// grow and a wide batch costs more device time per query than query-major
+// (8.8M index, 80k QPS: p50 2.9 ms with wide batches capped at 64, 4.0 ms
+// at 128), while a lone workspace call runs wide up to 128 queries (as
+// does a server without graphs: its batches run in the workspace's shape
+// for their size).
+constexpr uint32_t kTinyBatch = 64;    // graphs in the wide shape for up to 64 queries
 constexpr uint32_t kSmallBatch = 256;  // and for up to 256 queries
 
 struct Slot {
@@ -125,8 +132,8 @@ int make_slot(seismic_server* sv, Slot& s) {
         rc = seismic_graph_create(sv->index, s.ws, &q, s.d_nq, &p.search, s.d_ids, s.d_scores, nullptr, &s.graph);
         if (rc) return rc;
         // graphs for small and tiny batches, captured in the workspace's
-        // shapes for those sizes (unless configured: one wider workgroup per
-        // query up to 256 queries, the wide schedule up to 64)
+        // shapes for 256 and 64 queries (unless configured: one wider
+        // workgroup per query, and the wide schedule)
         if (nq > kSmallBatch) {
             seismic_csr qs{kSmallBatch, nnz, sv->index->h.dim, 1, s.d_ptr, s.d_words};
             rc = seismic_graph_create(sv->index, s.ws, &qs, s.d_nq, &p.search, s.d_ids, s.d_scores, nullptr,
