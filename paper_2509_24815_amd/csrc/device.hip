@@ -526,9 +526,9 @@ int seismic_workspace_resident_per_cu(const seismic_workspace* ws, uint32_t n_qu
     const seismic_launch_config& c = ws->cfg[bucket_of(n_queries)];
     DeviceGuard g(ws->device);
     if (!g.ok()) return fail(SEISMIC_EHIP, "resident: cannot select device");
-    // the kernel and LDS size the search launches for this shape (the wide
-    // schedule's traversal runs the same instance); the persistent grid is
-    // sized by the same occupancy query
+    // the occupancy query the search sizes its persistent grid by, for this
+    // shape's threads and this k's LDS (with the wide schedule it sizes the
+    // traversal's grid)
     const size_t smem = seismic_dev::search_smem_bytes(c.threads, ws->index->h.dim, ws->index->dev->sort_cap, k);
     int n = seismic_dev::search_blocks_per_cu(c.threads, smem);
     if (c.blocks_per_cu > 0) n = std::min<int>(n, (int)c.blocks_per_cu);
