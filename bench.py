@@ -540,10 +540,12 @@ def main():
                     docs_evaluated=float(cnt[:, 3].mean()), blocks_evaluated=float(cnt[:, 2].mean()),
                     layout_gbs=round(float(alg_bytes(cnt, q_nnz, k).sum()) / dt / 1e9, 1))
 
-    def search_grid(values, key, fn):
+    def search_grid(values, key, fn, bisections=3):
         """Walk values from most to least pruning; stop at the first point
-        that reaches the recall target, then bisect once between it and the
-        previous point.  Returns (chosen value, points)."""
+        that reaches the recall target, then bisect between it and the
+        previous point (up to `bisections` times) for the most pruning value
+        that still reaches it (recall is deterministic, so the choice is
+        too).  Returns (chosen value, points)."""
         pts, chosen, prev = [], None, None
         for v in values:
             pt = dict({key: v}, **fn(v))
@@ -553,13 +555,18 @@ def main():
                 chosen = v
                 break
             prev = v
-        if chosen is not None and prev is not None:
-            mid = round((prev + chosen) / 2, 4)
+        lo, hi = prev, chosen
+        for _ in range(bisections if chosen is not None and prev is not None else 0):
+            mid = round((lo + hi) / 2, 4)
+            if mid in (lo, hi):
+                break
             pt = dict({key: mid}, **fn(mid))
             pts.append(pt)
             log(f"[bench] sweep {pt}")
-            if pt["recall"] >= args.recall and pt["qps"] > next(p for p in pts if p[key] == chosen)["qps"]:
-                chosen = mid
+            if pt["recall"] >= args.recall:
+                hi = chosen = mid
+            else:
+                lo = mid
         return chosen, pts
 
     # operating point: for each query_cut, sweep heap_factor (Alg. 2 skip rule
