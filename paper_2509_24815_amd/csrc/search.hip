@@ -1024,6 +1024,25 @@ __device__ __forceinline__ Ingested ingest_query(const SearchArgs& a, const Sear
     return Ingested{q0, nqe, nvalid, ncut, status, u8mode};
 }
 
+// Step 1 for a row the list pass found valid, strictly ascending and of at
+// most kMaxSlots terms: entry j's term has slot j + 1, so the slot table and
+// the slot values are written straight from the row, with none of
+// ingest_query's checks and scans.  Every thread calls it; it ends with a
+// barrier; restore_region undoes it.
+template <int NT>
+__device__ __forceinline__ Ingested ingest_direct(const SearchArgs& a, const SearchLds<NT>& L, uint32_t qi) {
+    const int tid = threadIdx.x;
+    const uint64_t q1 = min(a.q_ptr[qi + 1], a.q_nnz), q0 = min(a.q_ptr[qi], q1);
+    const uint32_t n = (uint32_t)min<uint64_t>(q1 - q0, (uint64_t)kMaxSlots);
+    for (uint32_t j = tid; j < n; j += NT) {
+        const uint32_t w = a.q_words[q0 + j];
+        L.region[w & 0xFFFFu] = (uint8_t)(j + 1);
+        L.qv[j + 1] = (double)half_bits_to_float(w >> 16);
+    }
+    __syncthreads();
+    return Ingested{q0, n, n, 0u, 0u, true};
+}
+
 // Puts the lookup region of an ingested query back to all-zero.
 template <int NT>
 __device__ __forceinline__ void restore_region(const SearchArgs& a, const SearchLds<NT>& L, const Ingested& in) {
@@ -1241,7 +1260,12 @@ __global__ __launch_bounds__(NT) void k_wide_lists(SearchArgs a) {
                 a.wd_nspec[(size_t)qi * a.cmax + ci] = 0;
             }
         }
-        if (ci == 0 && tid == 0) a.wd_lb[qi] = 0.0f;  // the evaluation pass may raise it
+        if (ci == 0 && tid == 0) {
+            a.wd_lb[qi] = 0.0f;  // the evaluation pass may raise it
+            // a valid row of at most kMaxSlots terms: its slot table can be
+            // written straight from the row (ingest_direct)
+            a.wd_fast[qi] = (in.status == 0 && in.u8mode && in.nvalid == in.nqe) ? 1u : 0u;
+        }
         restore_region<NT>(a, L, in);
     }
 }
@@ -1329,7 +1353,10 @@ __global__ __launch_bounds__(kWideChunk) void k_wide_eval(SearchArgs a) {
         }
         if (qi != cur) {
             if (cur != 0xFFFFFFFFu) restore_region<NT>(a, L, in);
-            in = ingest_query<NT, false>(a, L, qi, nw);
+            if (a.wd_fast[qi])
+                in = ingest_direct<NT>(a, L, qi);
+            else
+                in = ingest_query<NT, false>(a, L, qi, nw);
             cur = qi;
         }
         top.which = 0;
@@ -1546,6 +1573,7 @@ hipError_t launch_search_wide(SearchArgs a, const WideSched& w, uint32_t nt, uin
     a.wd_ps = w.ps;
     a.wd_pid = w.pid;
     a.wd_lb = w.lb;
+    a.wd_fast = w.fast;
     // the traversal's own window for blocks past the speculated ones
     a.window = nt == 512 ? 16u : 8u;
     a.wd_nt = nt;
