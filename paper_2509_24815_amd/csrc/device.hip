@@ -192,7 +192,8 @@ int ensure_wide_sched(seismic_workspace* ws) {
     bool ok = al(w.r, lists * w.sort_cap * 4) && al(w.ord, lists * w.sort_cap * 2) && al(w.nspec, lists * 4) &&
               al(w.items, (size_t)w.icap * 16) && al(w.cnt, 16) && al(w.first, blocks * 4) &&
               al(w.docs, blocks * 4) && al(w.nnz, blocks * 8) && al(w.ps, (size_t)w.icap * w.k * 4) &&
-              al(w.pid, (size_t)w.icap * w.k * 4) && al(w.lb, (size_t)w.cap * 4) && al(w.fast, (size_t)w.cap * 4);
+              al(w.pid, (size_t)w.icap * w.k * 4) && al(w.lb, (size_t)w.cap * 4) && al(w.fast, (size_t)w.cap * 4) &&
+              al(w.cut, lists * 4);
     if (!ok) {
         for (void* x : ws->wd_allocs) (void)hipFree(x);
         ws->wd_allocs.clear();

@@ -1103,7 +1103,17 @@ __global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(Sear
         top.which = 0;
         top.hn = 0;
 
-        const Ingested in = ingest_query<NT, true>(a, L, qi, nw);
+        Ingested in;
+        uint32_t fast = 0;
+        if constexpr (WIDE) fast = a.wd_fast[qi];
+        if (fast) {  // the list pass checked the row and cut it
+            in = ingest_direct<NT>(a, L, qi);
+            in.ncut = fast - 1u;
+            if ((uint32_t)tid < in.ncut) L.cut[tid] = (uint16_t)a.wd_cut[(size_t)qi * a.cmax + tid];
+            __syncthreads();
+        } else {
+            in = ingest_query<NT, true>(a, L, qi, nw);
+        }
         const uint32_t ncut = in.ncut, nvalid = in.nvalid, status = in.status;
         const bool u8mode = in.u8mode;
 
@@ -1196,6 +1206,7 @@ __global__ __launch_bounds__(NT) void k_wide_lists(SearchArgs a) {
         if (ci >= in.ncut && tid == 0) a.wd_nspec[(size_t)qi * a.cmax + ci] = 0;  // past the cut: nothing speculated
         if (ci < in.ncut) {
             const uint32_t t = L.cut[ci];
+            if (tid == 0) a.wd_cut[(size_t)qi * a.cmax + ci] = t;
             const uint32_t b0 = ix.list_off[t], nb = ix.list_off[t + 1] - b0;
             if (nb) {
                 const uint64_t S0 = ix.blk_sum_off[b0], S1 = ix.blk_sum_off[b0 + nb];
@@ -1264,7 +1275,7 @@ __global__ __launch_bounds__(NT) void k_wide_lists(SearchArgs a) {
             a.wd_lb[qi] = 0.0f;  // the evaluation pass may raise it
             // a valid row of at most kMaxSlots terms: its slot table can be
             // written straight from the row (ingest_direct)
-            a.wd_fast[qi] = (in.status == 0 && in.u8mode && in.nvalid == in.nqe) ? 1u : 0u;
+            a.wd_fast[qi] = (in.status == 0 && in.u8mode && in.nvalid == in.nqe) ? 1u + in.ncut : 0u;
         }
         restore_region<NT>(a, L, in);
     }
@@ -1574,6 +1585,7 @@ hipError_t launch_search_wide(SearchArgs a, const WideSched& w, uint32_t nt, uin
     a.wd_pid = w.pid;
     a.wd_lb = w.lb;
     a.wd_fast = w.fast;
+    a.wd_cut = w.cut;
     // the traversal's own window for blocks past the speculated ones
     a.window = nt == 512 ? 16u : 8u;
     a.wd_nt = nt;

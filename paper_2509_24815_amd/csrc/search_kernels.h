@@ -76,7 +76,9 @@ struct SearchArgs {
     float* wd_ps;           // [wd_icap * k] top-k scores of each item's chunk (-inf padded)
     uint32_t* wd_pid;       // [wd_icap * k] and ids (0xFFFFFFFF padded)
     float* wd_lb;           // [nq] lower bound of every heap minimum after the query's first block (0: none)
-    uint32_t* wd_fast;      // [nq] 1: the row is valid with at most kMaxSlots terms (slot of entry j = j + 1)
+    uint32_t* wd_fast;      // [nq] 1 + cut lists when the row is valid with at most kMaxSlots terms (slot of
+                            // entry j = j + 1), else 0
+    uint32_t* wd_cut;       // [nq * cmax] term of every cut list (rows with wd_fast set)
 };
 
 constexpr uint32_t kModeQuery = 0, kModeList = 1, kModeWide = 2;
@@ -121,6 +123,7 @@ struct WideSched {
     uint32_t* pid = nullptr;
     float* lb = nullptr;
     uint32_t* fast = nullptr;
+    uint32_t* cut = nullptr;
     uint32_t cap = 0, sort_cap = 0, k = 0, icap = 0;
 };
 
