@@ -43,7 +43,7 @@ WORKLOADS = {
     # there: it does not fit the host's memory alongside its index
     "msmarco-v2-138M": dict(n_docs=138_000_000, n_queries=3903, qlaw="poisson", qmean=44.0, dmean=127.0,
                             lam=60000, beta=400, gamma=0.4, cut=10, hfs=(0.1, 0.15, 0.2) + HF_SWEEP,
-                            device_build=True),
+                            device_build=True, hot_hf=0.3),
 }
 
 PEAK_HBM_GBS = 8000.0
@@ -348,6 +348,11 @@ def main():
     ap.add_argument("--profile-copy", action="store_true", help="also run a plain copy for counter calibration")
     ap.add_argument("--index-cache", default=None, help="load the index from this file if present, else build and save")
     ap.add_argument("--plain-rows", action="store_true", help="search the forward rows in place (no block-major copies)")
+    ap.add_argument("--hot-sample", type=int, default=2000,
+                    help="device-built index: queries of a held-out sample whose most evaluated lists get block-major "
+                         "copies (0 = none)")
+    ap.add_argument("--hot-reserve-gb", type=float, default=8.0,
+                    help="device memory left free by the hot-list copies")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--schedule", type=int, default=None,
                     help="fix the launch shape to 256 threads, 3 per CU, window 8 and this schedule (0 query-major, "
@@ -387,7 +392,7 @@ def main():
 
     import torch
     import synth
-    from paper_2509_24815_amd import Index, binding
+    from paper_2509_24815_amd import Index, binding, hot_list_order
 
     for lib in (synth._LIB_PATH, binding.LIB_PATH):
         if not os.path.exists(lib):
@@ -503,6 +508,58 @@ def main():
     log(f"[bench] exact top-{k} of {nq} queries on the GPU: {exact_s:.2f} s")
     ex = ex_ids.cpu().numpy().view(np.uint32)
     ex_s = ex_sc.cpu().numpy()
+
+    hot = None
+    if on_device and not args.plain_rows and args.hot_sample > 0:
+        # the index reads its rows in place (copies of every list would not
+        # fit): block-major copies of the lists that a held-out sample of
+        # queries evaluates most, in the memory left once exact search's
+        # inverted index is freed
+        t3 = time.time()
+        ix.release_exact()
+        sample = synth.generate(args.hot_sample, seed=1, stream=synth.STREAM_QUERIES, law=W["qlaw"],
+                                mean=W["qmean"], lo=1, hi=400)
+        s_rp = torch.from_numpy(sample.row_ptr.astype(np.int64)).to(dev)
+        s_w = torch.from_numpy(sample.words.view(np.int32)).to(dev)
+        hf_s = args.hf if args.hf is not None else W.get("hot_hf", 0.3)
+        _, _, s_pre, _, _, s_term = ix.search(binding.device_csr(s_rp, s_w, sample.dim), k, cut, hf_s, trace=True,
+                                              prefix_stride=max(cut, 1))
+        torch.cuda.synchronize()
+        s_pre = s_pre.cpu().numpy().astype(np.uint16).astype(np.int64)
+        s_term = s_term.cpu().numpy().astype(np.int64)
+        order = hot_list_order(s_pre, s_term)
+        del s_rp, s_w
+        torch.cuda.empty_cache()
+
+        def batch_ms():  # the timed batch at the sample's heap_factor, the workspace's launch shape
+            for _ in range(2):
+                binding.seismic_search_batch(ix.handle, ws, qcsr, k, cut, hf_s, out_ids, out_sc, None, 0, None, stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                binding.seismic_search_batch(ix.handle, ws, qcsr, k, cut, hf_s, out_ids, out_sc, None, 0, None, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / args.steps, out_ids.cpu().numpy().copy(), out_sc.cpu().numpy().copy()
+
+        before_ms, before_ids, before_sc = batch_ms()
+        free, total = torch.cuda.mem_get_info()
+        budget = max(0, int(free - args.hot_reserve_gb * 1e9))
+        n_cp, used = ix.copy_lists(order, budget)
+        after_ms, after_ids, after_sc = batch_ms()
+        copied = np.zeros(qs.dim, dtype=bool)
+        copied[order[:n_cp]] = True
+        m = s_pre > 0
+        cover = float(s_pre[m][copied[s_term[m]]].sum() / max(1, s_pre[m].sum()))
+        free, total = torch.cuda.mem_get_info()
+        hot = {"lists_copied": n_cp, "lists_evaluated_by_sample": int(len(order)), "copies_gb": round(used / 1e9, 1),
+               "sample_queries": args.hot_sample, "sample_heap_factor": hf_s,
+               "sample_blocks_in_copied_lists": round(cover, 4), "build_s": round(time.time() - t3, 1),
+               "hbm_in_use_gb": round((total - free) / 1e9, 1),
+               "batch_ms_rows_in_place": round(before_ms, 3), "batch_ms_with_copies": round(after_ms, 3),
+               "same_results": bool(np.array_equal(before_ids, after_ids) and np.array_equal(before_sc, after_sc))}
+        layout = "rows in place + block-major copies of hot lists"
+        log(f"[bench] hot-list copies: {hot}")
 
     def recall_of(ids_np, sc_np, truth=None):
         t_ids, t_sc = (ex, ex_s) if truth is None else truth
@@ -1009,7 +1066,7 @@ def main():
                    "index_build": "cached" if build_s is None else
                    ("device-resident" if on_device else "host" if args.host_build else "gpu"),
                    "hbm": hbm, "exact_topk_s": round(exact_s, 2), "layout": layout, "launch": tuned,
-                   "grid": grid, "locality_order": locality},
+                   "grid": grid, "locality_order": locality, "hot_copies": hot},
         "forms": forms,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,

@@ -208,7 +208,8 @@ int seismic_index_load(const char* path, seismic_index** out);
 
 /* out[0..7] = dim, n_docs, nnz, n_blocks, n_postings, n_summary entries,
    lambda, beta; out[8] = largest number of blocks in one list; out[9] = 1
-   when the index is resident on a device (2 with block-major rows). */
+   when the index is resident on a device (2 with block-major copies of the
+   rows of every list, 3 of some lists). */
 int seismic_index_info(const seismic_index* index, uint64_t out[10]);
 
 /* Copy the index to HBM of HIP device `device` (synchronous).  Required
@@ -220,6 +221,24 @@ int seismic_index_info(const seismic_index* index, uint64_t out[10]);
    nonzero per posting of device memory and never changes results. */
 #define SEISMIC_UPLOAD_BLOCK_ROWS 1u
 int seismic_index_upload(seismic_index* index, int device, uint32_t flags);
+
+/* Block evaluation (Algorithm 2, Section 4.5) reads the forward rows of a
+   block's documents.  This stores the block-major copies that
+   SEISMIC_UPLOAD_BLOCK_ROWS makes for every list for the lists
+   lists[0..n_lists) (term ids, most valuable first) only, for an index
+   resident on a device, uploaded or device-built, whose copies of every
+   list would not fit: the longest prefix of lists[] whose copies fit in
+   max_bytes of device memory is copied (16-byte padded rows, 12 bytes of
+   offsets per posting and 4 bytes per block of the index).  Blocks of
+   other lists keep reading their rows in place; results never change.
+   *n_copied (nullable) = the length of that prefix, *bytes (nullable) =
+   the device memory taken.  EINVAL for a term id >= dim or one given
+   twice; ESTATE when the index is not resident or already has copies;
+   ENOMEM when device memory runs out (nothing is kept).  Synchronous.  Not
+   concurrently with searches on this index; launches made afterwards read
+   the copies (graphs captured before keep reading rows in place). */
+int seismic_index_copy_lists(seismic_index* index, const uint32_t* lists, uint32_t n_lists, uint64_t max_bytes,
+                             uint32_t* n_copied, uint64_t* bytes);
 
 /* Release host and device memory of the index. */
 void seismic_index_free(seismic_index* index);
@@ -359,6 +378,11 @@ int seismic_search_batch_noalloc(const seismic_index* index, const seismic_csr* 
  */
 int exact_topk(const seismic_index* index, const seismic_csr* queries, uint32_t k, uint32_t* out_ids,
                float* out_scores, void* stream);
+
+/* Free the inverted index that exact_topk built (a later exact_topk builds
+ * it again).  Waits for the device to finish its work first.  A no-op when
+ * there is none. */
+int seismic_index_release_exact(seismic_index* index);
 
 /* ------------------------------------------------------- kappa-NN graph
  * The graph of Section 4.3: N(u) = the kappa documents v != u with the

@@ -9,7 +9,24 @@ from __future__ import annotations
 from . import binding
 from .binding import SeismicError
 
-__all__ = ["binding", "Index", "SeismicError"]
+__all__ = ["binding", "Index", "SeismicError", "hot_list_order"]
+
+
+def hot_list_order(prefix, list_term):
+    """Term ids of the lists a traced batch evaluated blocks of, the most
+    evaluated blocks first (ties by smaller term id).  prefix[q, i] blocks
+    of list list_term[q, i] were evaluated (the search trace); positions
+    with a zero prefix are ignored.  The order in which to give lists block-
+    major copies when not every list fits (Index.copy_lists)."""
+    import numpy as np
+    p = np.asarray(prefix).astype(np.uint16).astype(np.int64).ravel()
+    t = np.asarray(list_term).astype(np.int64).ravel()
+    m = p > 0
+    if not m.any():
+        return np.zeros(0, dtype=np.uint32)
+    w = np.bincount(t[m], weights=p[m])
+    terms = np.nonzero(w)[0]
+    return terms[np.lexsort((terms, -w[terms]))].astype(np.uint32)
 
 
 class Index:
@@ -54,6 +71,25 @@ class Index:
 
     def upload(self, device: int = 0, block_rows: bool = False):
         binding.seismic_index_upload(self.handle, device, block_rows)
+
+    def copy_lists(self, lists, max_bytes: int):
+        """Block-major row copies of the longest prefix of ``lists`` that fits
+        max_bytes of device memory: (entries covered, bytes taken)."""
+        return binding.seismic_index_copy_lists(self.handle, lists, max_bytes)
+
+    def copy_hot_lists(self, sample_queries, k: int, query_cut: int, heap_factor: float, max_bytes: int):
+        """Copies for the lists a sample batch evaluates most (hot_list_order
+        of its trace).  Returns (lists covered, bytes taken, the order)."""
+        import torch
+        _, _, prefix, _, _, term = self.search(sample_queries, k, query_cut, heap_factor, trace=True)
+        torch.cuda.synchronize()
+        order = hot_list_order(prefix.cpu().numpy(), term.cpu().numpy())
+        n, used = self.copy_lists(order, max_bytes)
+        return n, used, order
+
+    def release_exact(self):
+        """Free the inverted index built by exact search."""
+        binding.seismic_index_release_exact(self.handle)
 
     def workspace(self, max_queries: int, max_k: int) -> int:
         key = (max_queries, max_k)

@@ -106,6 +106,8 @@ def load():
         "seismic_index_load": ([ctypes.c_char_p, P(vp)], i32),
         "seismic_index_info": ([vp, vp], i32),
         "seismic_index_upload": ([vp, i32, u32], i32),
+        "seismic_index_copy_lists": ([vp, vp, u32, u64, P(u32), P(u64)], i32),
+        "seismic_index_release_exact": ([vp], i32),
         "seismic_index_free": ([vp], None),
         "seismic_workspace_create": ([vp, u32, u32, P(vp)], i32),
         "seismic_workspace_free": ([vp], None),
@@ -241,6 +243,21 @@ def seismic_index_info(handle) -> dict:
 
 def seismic_index_upload(handle, device: int = 0, block_rows: bool = False):
     _check(load().seismic_index_upload(handle, device, 1 if block_rows else 0))
+
+
+def seismic_index_copy_lists(handle, lists, max_bytes: int):
+    """Block-major row copies of the longest prefix of `lists` (term ids,
+    most valuable first) fitting max_bytes of device memory.  Returns
+    (entries of lists covered, device bytes taken)."""
+    arr = np.ascontiguousarray(np.asarray(lists, dtype=np.uint32))
+    n_copied, used = ctypes.c_uint32(0), ctypes.c_uint64(0)
+    _check(load().seismic_index_copy_lists(handle, arr.ctypes.data if arr.size else None, arr.size,
+                                           int(max_bytes), ctypes.byref(n_copied), ctypes.byref(used)))
+    return int(n_copied.value), int(used.value)
+
+
+def seismic_index_release_exact(handle):
+    _check(load().seismic_index_release_exact(handle))
 
 
 def seismic_index_free(handle):

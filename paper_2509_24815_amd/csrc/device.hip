@@ -12,7 +12,7 @@
 using namespace seismic;
 using seismic_dev::DevIdx;
 
-int device_index_layout(const DeviceIndex* d) { return !d ? 0 : d->view.brow ? 2 : 1; }
+int device_index_layout(const DeviceIndex* d) { return !d ? 0 : !d->view.brow ? 1 : d->copy_all ? 2 : 3; }
 
 void device_index_free(DeviceIndex* d) {
     if (!d) return;
@@ -290,54 +290,216 @@ int launch_batch(const seismic_index* index, seismic_workspace* ws, const uint64
     return SEISMIC_OK;
 }
 
-// Copy the row of posting p (document postings[p]) to 16-byte groups
-// [prow[p], prow[p+1]) of brow, zero-padded.  One wave per posting.
-__global__ __launch_bounds__(256) void k_build_block_rows(const uint64_t* row_ptr, const uint32_t* words,
-                                                          const uint32_t* postings, const uint64_t* prow,
-                                                          uint64_t n_postings, uint32_t* brow) {
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t n_waves = (uint64_t)gridDim.x * blockDim.x / 64;
-    for (uint64_t p = wave; p < n_postings; p += n_waves) {
-        const uint32_t d = postings[p];
-        const uint64_t rs = row_ptr[d], len = row_ptr[d + 1] - rs;
-        const uint64_t dst = prow[p] * 4, n = (prow[p + 1] - prow[p]) * 4;
-        for (uint64_t i = lane; i < n; i += 64) brow[dst + i] = i < len ? words[rs + i] : 0u;
+// Block-major copies of the rows of selected lists.  Selected list j holds
+// the postings [gp[j], gp[j] + cb[j + 1] - cb[j]) and owns the copies
+// [cb[j], cb[j + 1]), one per posting, in posting order: the rows of a block
+// are one contiguous run.  Each row is padded with zero words to whole
+// 16-byte groups.
+
+// groups[j] = the 16-byte groups of list j's copies.  One workgroup per list.
+__global__ __launch_bounds__(256) void k_copy_groups(const uint64_t* row_ptr, const uint32_t* postings,
+                                                     const uint64_t* gp, const uint64_t* cb, uint64_t* groups) {
+    __shared__ unsigned long long red[256 / seismic_dev::kWave];
+    const uint32_t j = blockIdx.x;
+    const uint64_t p0 = gp[j], n = cb[j + 1] - cb[j];
+    unsigned long long s = 0;
+    for (uint64_t i = threadIdx.x; i < n; i += 256) {
+        const uint32_t d = postings[p0 + i];
+        s += (row_ptr[d + 1] - row_ptr[d] + 3) / 4;
+    }
+    s = seismic_dev::wave_sum(s);
+    if ((threadIdx.x & (seismic_dev::kWave - 1)) == 0) red[threadIdx.x / seismic_dev::kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 256 / seismic_dev::kWave; ++w) t += red[w];
+        groups[j] = t;
     }
 }
 
-// Block-major copies of the rows: posting order is block order, so the
-// rows of a block are one contiguous run.
-int build_block_rows(DeviceIndex* d, const HostIndex& h) {
-    const uint64_t np = h.postings.size();
-    std::vector<uint64_t> prow(np + 1);
-    std::vector<uint32_t> pnnz(np);
-    uint64_t run = 0;
-    for (uint64_t p = 0; p < np; ++p) {
-        const uint32_t doc = h.postings[p];
-        const uint64_t len = h.row_ptr[doc + 1] - h.row_ptr[doc];
-        prow[p] = run;
-        pnnz[p] = (uint32_t)len;
-        run += (len + 3) / 4;
+// prow[c] = first group of copy c (list j's copies start at group
+// gbase[j]), pnnz[c] = its nonzeros.  One workgroup per list, a scan over
+// chunks of 256 copies with a running carry.
+__global__ __launch_bounds__(256) void k_copy_offsets(const uint64_t* row_ptr, const uint32_t* postings,
+                                                      const uint64_t* gp, const uint64_t* cb, const uint64_t* gbase,
+                                                      uint64_t* prow, uint32_t* pnnz) {
+    __shared__ uint32_t scratch[256 / seismic_dev::kWave];
+    const uint32_t j = blockIdx.x;
+    const uint64_t p0 = gp[j], c0 = cb[j], n = cb[j + 1] - c0;
+    uint64_t carry = gbase[j];
+    for (uint64_t base = 0; base < n; base += 256) {
+        const uint64_t i = base + threadIdx.x;
+        uint32_t len = 0;
+        if (i < n) {
+            const uint32_t d = postings[p0 + i];
+            len = (uint32_t)(row_ptr[d + 1] - row_ptr[d]);
+        }
+        uint32_t tot;
+        const uint32_t ex = seismic_dev::block_exscan<256>((len + 3) / 4, scratch, &tot);
+        if (i < n) {
+            prow[c0 + i] = carry + ex;
+            pnnz[c0 + i] = len;
+        }
+        carry += tot;
     }
-    prow[np] = run;
+}
+
+// The rows themselves: one wave per copy.
+__global__ __launch_bounds__(256) void k_copy_rows(const uint64_t* row_ptr, const uint32_t* words,
+                                                   const uint32_t* postings, const uint64_t* gp, const uint64_t* cb,
+                                                   uint32_t n_lists, const uint64_t* prow, const uint32_t* pnnz,
+                                                   uint32_t* brow) {
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / seismic_dev::kWave;
+    const uint32_t lane = threadIdx.x & (seismic_dev::kWave - 1);
+    const uint64_t n_waves = (uint64_t)gridDim.x * blockDim.x / seismic_dev::kWave, n = cb[n_lists];
+    for (uint64_t c = wave; c < n; c += n_waves) {
+        uint32_t lo = 0, hi = n_lists;  // the list of copy c: cb[lo] <= c < cb[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (cb[mid] <= c) lo = mid; else hi = mid;
+        }
+        const uint32_t d = postings[gp[lo] + (c - cb[lo])];
+        const uint64_t rs = row_ptr[d], len = pnnz[c];
+        const uint64_t dst = prow[c] * 4, m = (len + 3) / 4 * 4;
+        for (uint64_t i = lane; i < m; i += seismic_dev::kWave) brow[dst + i] = i < len ? words[rs + i] : 0u;
+    }
+}
+
+// Device buffers of one call, freed on every return unless released.
+struct CallBuffers {
+    std::vector<void*> p;
+    ~CallBuffers() {
+        if (p.empty()) return;
+        (void)hipDeviceSynchronize();  // kernels of a failed call may still read them
+        for (void* x : p) (void)hipFree(x);
+    }
+    int alloc(void** out, size_t bytes, const char* what) {
+        *out = nullptr;
+        hipError_t e = hipMalloc(out, std::max<size_t>(bytes, 16));
+        if (e != hipSuccess)
+            return fail(SEISMIC_ENOMEM, "block-major copies: %s needs %zu bytes: %s", what, bytes, hipGetErrorString(e));
+        p.push_back(*out);
+        return SEISMIC_OK;
+    }
+    template <typename T>
+    int put(T** out, const std::vector<T>& v, const char* what) {
+        int rc = alloc((void**)out, v.size() * sizeof(T), what);
+        if (!rc && !v.empty()) HIP_TRY(hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        return rc;
+    }
+};
+
+// Builds the copies of lists[0..n) (term ids, in priority order) for the
+// longest prefix whose copies fit in max_bytes of device memory, counting
+// the rows, 12 bytes of offsets per posting and the per-block map.
+int build_copies(DeviceIndex* d, const HostIndex& h, const uint32_t* lists, uint32_t n, uint64_t max_bytes,
+                 bool all, uint32_t* n_copied, uint64_t* bytes_used) {
     DevIdx& v = d->view;
-    int rc = upload_vec(d, prow, v.prow);
-    if (!rc) rc = upload_vec(d, pnnz, v.pnnz);
-    if (rc) return rc;
-    void* brow = nullptr;
-    const size_t bytes = (size_t)(run + 2) * 16;  // +2 groups: vector loads past the end stay inside
-    hipError_t e = hipMalloc(&brow, bytes);
-    if (e != hipSuccess) return fail(SEISMIC_ENOMEM, "upload: block-major rows need %zu bytes: %s", bytes, hipGetErrorString(e));
-    d->allocs.push_back(brow);
-    HIP_TRY(hipMemset((uint8_t*)brow + run * 16, 0, 32));
-    if (np) {
-        hipLaunchKernelGGL(k_build_block_rows, dim3(8192), dim3(256), 0, nullptr, v.row_ptr, v.words, v.postings, v.prow,
-                           np, (uint32_t*)brow);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipDeviceSynchronize());
+    if (n_copied) *n_copied = 0;
+    if (bytes_used) *bytes_used = 0;
+    if (v.bcopy) return fail(SEISMIC_ESTATE, "block-major copies: the index already has them");
+    if (n && !lists) return fail(SEISMIC_EINVAL, "block-major copies: null list array");
+    std::vector<uint8_t> seen(h.dim, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (lists[i] >= h.dim) return fail(SEISMIC_EINVAL, "block-major copies: list %u >= dim %u", lists[i], h.dim);
+        if (seen[lists[i]]++) return fail(SEISMIC_EINVAL, "block-major copies: list %u given twice", lists[i]);
     }
-    v.brow = (const uint32_t*)brow;
+    // the selected lists that hold postings, with their postings and copies
+    std::vector<uint32_t> term;
+    std::vector<uint64_t> gp, cb(1, 0);
+    auto empty = [&](uint32_t t) { return h.blk_post_off[h.list_off[t]] == h.blk_post_off[h.list_off[t + 1]]; };
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t t = lists[i];
+        if (empty(t)) continue;
+        const uint64_t p0 = h.blk_post_off[h.list_off[t]], np = h.blk_post_off[h.list_off[t + 1]] - p0;
+        if (cb.back() + np >= seismic_dev::kNoCopy) {  // copy indexes are 32-bit
+            if (all) return fail(SEISMIC_EINVAL, "block-major copies: more than 2^32 - 2 postings");
+            break;
+        }
+        term.push_back(t);
+        gp.push_back(p0);
+        cb.push_back(cb.back() + np);
+    }
+    uint32_t J = (uint32_t)term.size();
+    // entries of lists[] covered by the first J' selected lists: those
+    // copied, and lists without postings among and right after them
+    auto covered = [&](uint32_t Jc) {
+        uint32_t i = 0, j = 0;
+        while (i < n && (empty(lists[i]) || (j < Jc && lists[i] == term[j]))) {
+            if (!empty(lists[i])) ++j;
+            ++i;
+        }
+        return i;
+    };
+    if (J == 0) {
+        if (n_copied) *n_copied = covered(0);
+        return SEISMIC_OK;
+    }
+    CallBuffers tmp;
+    uint64_t *d_gp = nullptr, *d_cb = nullptr, *d_groups = nullptr;
+    int rc = tmp.put(&d_gp, gp, "list offsets");
+    if (!rc) rc = tmp.put(&d_cb, cb, "list offsets");
+    if (!rc) rc = tmp.alloc((void**)&d_groups, (size_t)J * 8, "list sizes");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_copy_groups, dim3(J), dim3(256), 0, nullptr, v.row_ptr, v.postings, d_gp, d_cb, d_groups);
+    HIP_TRY(hipGetLastError());
+    std::vector<uint64_t> groups(J);
+    HIP_TRY(hipMemcpy(groups.data(), d_groups, (size_t)J * 8, hipMemcpyDeviceToHost));
+    // the longest prefix that fits
+    const uint64_t nb = h.list_off[h.dim];
+    const uint64_t fixed = nb * 4 + 32 + 16;
+    std::vector<uint64_t> gbase(J + 1, 0);
+    uint32_t keep = 0;
+    for (uint32_t j = 0; j < J; ++j) {
+        gbase[j + 1] = gbase[j] + groups[j];
+        const uint64_t need = fixed + gbase[j + 1] * 16 + cb[j + 1] * 12;
+        if (!all && need > max_bytes) break;
+        keep = j + 1;
+    }
+    if (keep == 0) {
+        if (n_copied) *n_copied = covered(0);
+        return SEISMIC_OK;
+    }
+    J = keep;
+    const uint64_t nc = cb[J], ng = gbase[J];
+    uint64_t *d_gbase = nullptr, *prow = nullptr;
+    uint32_t *pnnz = nullptr, *brow = nullptr, *bcopy = nullptr;
+    gbase.resize(J);
+    rc = tmp.put(&d_gbase, gbase, "list offsets");
+    if (!rc) rc = tmp.alloc((void**)&prow, nc * 8, "row offsets");
+    if (!rc) rc = tmp.alloc((void**)&pnnz, nc * 4, "row lengths");
+    // +2 groups: vector loads past the last row stay inside
+    if (!rc) rc = tmp.alloc((void**)&brow, (ng + 2) * 16, "rows");
+    if (!rc) rc = tmp.alloc((void**)&bcopy, nb * 4, "block map");
+    if (rc) return rc;
+    HIP_TRY(hipMemset((uint8_t*)brow + ng * 16, 0, 32));
+    hipLaunchKernelGGL(k_copy_offsets, dim3(J), dim3(256), 0, nullptr, v.row_ptr, v.postings, d_gp, d_cb, d_gbase,
+                       prow, pnnz);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_copy_rows, dim3(8192), dim3(256), 0, nullptr, v.row_ptr, v.words, v.postings, d_gp, d_cb, J,
+                       prow, pnnz, brow);
+    HIP_TRY(hipGetLastError());
+    std::vector<uint32_t> map(nb, seismic_dev::kNoCopy);
+    for (uint32_t j = 0; j < J; ++j)
+        for (uint32_t b = h.list_off[term[j]]; b < h.list_off[term[j] + 1]; ++b)
+            map[b] = (uint32_t)(cb[j] + (h.blk_post_off[b] - gp[j]));
+    HIP_TRY(hipMemcpy(bcopy, map.data(), nb * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipDeviceSynchronize());
+    // the copies now belong to the index
+    for (void* x : {(void*)prow, (void*)pnnz, (void*)brow, (void*)bcopy}) {
+        tmp.p.erase(std::find(tmp.p.begin(), tmp.p.end(), x));
+        d->allocs.push_back(x);
+    }
+    v.prow = prow;
+    v.pnnz = pnnz;
+    v.brow = brow;
+    v.bcopy = bcopy;
+    std::vector<uint8_t> done(h.dim, 0);
+    for (uint32_t j = 0; j < J; ++j) done[term[j]] = 1;
+    d->copy_all = true;
+    for (uint32_t t = 0; t < h.dim; ++t) d->copy_all = d->copy_all && (done[t] || empty(t));
+    if (n_copied) *n_copied = covered(J);
+    if (bytes_used) *bytes_used = fixed + ng * 16 + nc * 12;
     return SEISMIC_OK;
 }
 
@@ -435,12 +597,43 @@ int seismic_index_upload(seismic_index* index, int device, uint32_t flags) {
     if (!rc) rc = upload_vec(d, h.postings, v.postings);
     if (!rc) rc = upload_vec(d, h.sum_term, v.sum_term, 16);
     if (!rc) rc = upload_vec(d, h.sum_code, v.sum_code, 16);
-    if (!rc && (flags & SEISMIC_UPLOAD_BLOCK_ROWS)) rc = build_block_rows(d, h);
+    if (!rc && (flags & SEISMIC_UPLOAD_BLOCK_ROWS)) {
+        std::vector<uint32_t> all(h.dim);
+        for (uint32_t t = 0; t < h.dim; ++t) all[t] = t;
+        rc = build_copies(d, h, all.data(), h.dim, 0, true, nullptr, nullptr);
+    }
     if (!rc) rc = device_term_rank(d, h.list_off, h.dim);
     if (rc) { device_index_free(d); return rc; }
     v.dim = h.dim;
     v.n_docs = (uint32_t)h.n_docs;
     index->dev = d;
+    return SEISMIC_OK;
+}
+
+int seismic_index_copy_lists(seismic_index* index, const uint32_t* lists, uint32_t n_lists, uint64_t max_bytes,
+                             uint32_t* n_copied, uint64_t* bytes) {
+    if (!index) return fail(SEISMIC_EINVAL, "copy lists: null index");
+    std::lock_guard<std::mutex> lk(index->mu);
+    if (!index->dev) return fail(SEISMIC_ESTATE, "copy lists: index is not on a device");
+    DeviceGuard g(index->dev->device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "copy lists: cannot select device %d", index->dev->device);
+    return build_copies(index->dev, index->h, lists, n_lists, max_bytes, false, n_copied, bytes);
+}
+
+int seismic_index_release_exact(seismic_index* index) {
+    if (!index) return fail(SEISMIC_EINVAL, "release exact: null index");
+    std::lock_guard<std::mutex> lk(index->mu);
+    DeviceIndex* d = index->dev;
+    if (!d || !d->csc_off) return SEISMIC_OK;
+    DeviceGuard g(d->device);
+    if (!g.ok()) return fail(SEISMIC_EHIP, "release exact: cannot select device %d", d->device);
+    HIP_TRY(hipDeviceSynchronize());  // exact searches in flight still read them
+    (void)hipFree(d->csc_off);
+    (void)hipFree(d->csc_doc);
+    (void)hipFree(d->csc_val);
+    d->csc_off = nullptr;
+    d->csc_doc = nullptr;
+    d->csc_val = nullptr;
     return SEISMIC_OK;
 }
 

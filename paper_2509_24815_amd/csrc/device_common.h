@@ -7,6 +7,7 @@
 namespace seismic_dev {
 
 constexpr int kWave = 64;
+constexpr uint32_t kNoCopy = 0xFFFFFFFFu;
 
 // The index as the kernels see it (all device pointers).
 struct DevIdx {
@@ -20,8 +21,12 @@ struct DevIdx {
     const uint32_t* postings;
     const uint16_t* sum_term;  // padded to a multiple of 8 entries (+8)
     const uint8_t* sum_code;   // padded likewise
-    // block-major rows (optional): posting p's row occupies 16-byte groups
-    // [prow[p], prow[p+1]) of brow, zero-padded; pnnz[p] = its nonzeros
+    // block-major copies of the rows of some or all lists (optional): block
+    // b's postings have copies c = bcopy[b] + (p - blk_post_off[b]), or none
+    // when bcopy[b] == kNoCopy (always the same for the blocks of one list);
+    // copy c's row occupies 16-byte groups [prow[c], prow[c] + ceil(pnnz[c]
+    // / 4)) of brow, zero-padded, and pnnz[c] is its number of nonzeros
+    const uint32_t* bcopy;
     const uint64_t* prow;
     const uint32_t* pnnz;
     const uint32_t* brow;

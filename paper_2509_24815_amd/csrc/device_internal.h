@@ -37,6 +37,8 @@ struct DeviceIndex {
     // [dim] rank of every list by block count (descending, then term):
     // the order of the list-major schedule's items
     uint32_t* term_rank = nullptr;
+    // the block-major copies (view.bcopy) cover every list with postings
+    bool copy_all = false;
 };
 
 // Fills d->term_rank from the list offsets (host) of the index.

@@ -10,7 +10,7 @@
 #include "internal.h"
 
 void device_index_free(DeviceIndex* d);          // device.hip
-int device_index_layout(const DeviceIndex* d);  // 0 none, 1 resident, 2 with block-major rows
+int device_index_layout(const DeviceIndex* d);  // 0 none, 1 resident, 2 with block-major copies of every list, 3 of some
 
 namespace seismic {
 

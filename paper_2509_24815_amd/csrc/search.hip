@@ -291,11 +291,12 @@ __device__ __forceinline__ void summary_group(const SearchLds<NT>& L, const Look
 // (words outside the row are replaced by 0, which adds exactly 0) with
 // kUnroll loads per document in flight, and reduce with shuffles.  On return
 // cacc[t] is the exact score of document t (fp64) and clen[t] its number of
-// nonzeros.  Every thread calls it; it ends with a barrier.  BR: the index
-// holds block-major rows (16-byte aligned, zero-padded: no masking needed).
+// nonzeros.  Every thread calls it; it ends with a barrier.  BR: the
+// window's list has block-major copies of its rows (16-byte aligned,
+// zero-padded: no masking needed), posting p's at copy p + cbias.
 template <int NT, typename Look, bool BR>
 __device__ inline void gather_and_score_t(const DevIdx& ix, const SearchLds<NT>& L, const Look& look, uint32_t tot,
-                                          uint32_t nwb, uint32_t big_off) {
+                                          uint32_t nwb, uint32_t big_off, int64_t cbias) {
     const int tid = threadIdx.x;
     if ((uint32_t)tid < tot) {
         uint32_t s = 0;
@@ -305,8 +306,9 @@ __device__ inline void gather_and_score_t(const DevIdx& ix, const SearchLds<NT>&
         uint64_t rs;
         uint32_t len;
         if (BR) {  // block-major copy: contiguous with its neighbours, 16-byte aligned
-            rs = ix.prow[p] << 2;
-            len = ix.pnnz[p];
+            const uint64_t c = (uint64_t)((int64_t)p + cbias);
+            rs = ix.prow[c] << 2;
+            len = ix.pnnz[c];
         } else {
             rs = ix.row_ptr[d];
             len = (uint32_t)(ix.row_ptr[d + 1] - rs);
@@ -370,13 +372,23 @@ __device__ inline void gather_and_score_t(const DevIdx& ix, const SearchLds<NT>&
     __syncthreads();
 }
 
+// Offset from a posting of block b (whose first posting is p0) to its
+// block-major copy, or kNoBias when the block's list has no copies.
+constexpr int64_t kNoBias = INT64_MIN;
+__device__ __forceinline__ int64_t copy_bias(const DevIdx& ix, uint32_t b, uint32_t p0) {
+    if (!ix.bcopy) return kNoBias;
+    const uint32_t c = __builtin_amdgcn_readfirstlane(ix.bcopy[b]);
+    return c == kNoCopy ? kNoBias : (int64_t)c - (int64_t)p0;
+}
+
+// cbias: copy_bias of the window's list (the same for all its blocks).
 template <int NT, typename Look>
 __device__ inline void gather_and_score(const DevIdx& ix, const SearchLds<NT>& L, const Look& look, uint32_t tot,
-                                        uint32_t nwb, uint32_t big_off) {
-    if (ix.brow)
-        gather_and_score_t<NT, Look, true>(ix, L, look, tot, nwb, big_off);
+                                        uint32_t nwb, uint32_t big_off, int64_t cbias) {
+    if (cbias != kNoBias)
+        gather_and_score_t<NT, Look, true>(ix, L, look, tot, nwb, big_off, cbias);
     else
-        gather_and_score_t<NT, Look, false>(ix, L, look, tot, nwb, big_off);
+        gather_and_score_t<NT, Look, false>(ix, L, look, tot, nwb, big_off, 0);
 }
 
 // Fold the gathered documents of window slot `slot` (all of them when
@@ -615,6 +627,8 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
             if (a.prefix && tid == 0 && ci < a.prefix_stride) a.prefix[(size_t)qi * a.prefix_stride + ci] = 0;
             continue;
         }
+        const uint32_t ub0 = __builtin_amdgcn_readfirstlane(b0);
+        const int64_t cbias = copy_bias(ix, ub0, __builtin_amdgcn_readfirstlane(ix.blk_post_off[ub0]));
         // ---------------------------------------- a. summary scores
         uint64_t S0, S1;
         if constexpr (WIDE) {
@@ -784,7 +798,7 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
                     const uint32_t n = min((uint32_t)NT, tot - c0);
                     if (tid == 0) { L.wst[0] = 0; L.wst[1] = n; }
                     __syncthreads();
-                    gather_and_score<NT, Look>(ix, L, look, n, 1, c0);
+                    gather_and_score<NT, Look>(ix, L, look, n, 1, c0, cbias);
                     fold_slot<NT>(L, top, n, -1, C.nnz);
                 }
                 ++pos;
@@ -797,7 +811,7 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
                 L.wst[nwb] = run;
             }
             __syncthreads();
-            gather_and_score<NT, Look>(ix, L, look, tot, nwb, 0);
+            gather_and_score<NT, Look>(ix, L, look, tot, nwb, 0, cbias);
             wdocs = tot;
             }
             if constexpr (WIDE) {
@@ -1374,12 +1388,13 @@ __global__ __launch_bounds__(kWideChunk) void k_wide_eval(SearchArgs a) {
         top.hn = 0;
         const uint32_t p0 = ix.blk_post_off[b], n = ix.blk_post_off[b + 1] - p0;
         const uint32_t c0 = c * NT, m = min((uint32_t)NT, n - c0);
+        const int64_t cbias = copy_bias(ix, b, p0);
         if (tid == 0) { L.wst[0] = 0; L.wst[1] = m; L.wp0[0] = p0; }
         __syncthreads();
         if (in.u8mode)
-            gather_and_score<NT, LookU8>(ix, L, LookU8{L.region, L.qv}, m, 1, c0);
+            gather_and_score<NT, LookU8>(ix, L, LookU8{L.region, L.qv}, m, 1, c0, cbias);
         else
-            gather_and_score<NT, LookBits>(ix, L, LookBits{L.bq}, m, 1, c0);
+            gather_and_score<NT, LookBits>(ix, L, LookBits{L.bq}, m, 1, c0, cbias);
         uint64_t nnz = 0;
         fold_slot<NT>(L, top, m, -1, nnz);
         const unsigned long long v = wave_sum((unsigned long long)nnz);

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from paper_2509_24815_amd import Index, SeismicError, binding
+from paper_2509_24815_amd import Index, SeismicError, binding, hot_list_order
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "seismic.h")
@@ -110,6 +110,23 @@ def test_search_requires_device_index(small):
     with pytest.raises(SeismicError) as e:
         binding.seismic_workspace_create(ix.handle, 10, 10)
     assert e.value.code == binding.ESTATE
+    with pytest.raises(SeismicError) as e:  # block-major copies need the resident index
+        ix.copy_lists([0, 1], 1 << 40)
+    assert e.value.code == binding.ESTATE
+    ix.release_exact()  # nothing to free: no error
+
+
+def test_hot_list_order():
+    # prefix[q, i] blocks of list term[q, i] evaluated; zero prefixes (lists
+    # never evaluated, unused positions with any term) do not count
+    prefix = np.array([[3, 1, 0], [2, 0, 0], [1, 4, 0]], dtype=np.int16)
+    term = np.array([[7, 2, 9], [2, 5, 11], [4, 7, 30000]], dtype=np.int32)
+    # totals: 7 -> 7, 2 -> 3, 4 -> 1; ties broken by smaller term id
+    assert hot_list_order(prefix, term).tolist() == [7, 2, 4]
+    assert hot_list_order(np.array([[1, 1]]), np.array([[9, 3]])).tolist() == [3, 9]
+    assert hot_list_order(np.zeros((2, 2)), np.ones((2, 2))).size == 0
+    # prefixes above 2^15 arrive as negative int16
+    assert hot_list_order(np.array([[-1, 5]], dtype=np.int16), np.array([[1, 2]])).tolist() == [1, 2]
 
 
 def test_empty_and_degenerate_collections():
