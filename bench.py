@@ -332,6 +332,26 @@ def serve_run(binding, ix, qs, rate, seconds, k, cut, hf, probe, tau, max_batch=
             "max_inflight": st["max_inflight"], "slots": slots, "max_batch": max_batch}
 
 
+def grid_1m_leg():
+    """The 1M-document configuration's query_cut x heap_factor grid (10k
+    Poisson(43) queries, k 10), run by this script in a child process; its
+    progress goes to stderr."""
+    import subprocess
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--workload", "1M", "--grid", "5,10,20x0.7,0.8,0.9",
+           "--no-serve", "--knn", "0", "--probe", "none", "--cpu-seconds", "0", "--no-k100", "--no-unique",
+           "--steps", "5", "--warmup", "1"]
+    log("[bench] 1M grid: " + " ".join(cmd[2:]))
+    t0 = time.time()
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
+    if r.returncode != 0:
+        return {"error": f"exit status {r.returncode}"}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"qps": d["value"], "recall_at_10": d["config"]["recall_at_10"], "ms_per_step": d["ms_per_step"],
+            "workload": d["config"]["workload"], "frac": d["roofline"]["frac"],
+            "layout_frac": d["roofline"]["layout_frac"], "grid": d["config"]["grid"],
+            "seconds": round(time.time() - t0, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,6 +388,8 @@ def main():
                          "cut for k <= 10, else 10,15,20,30)")
     ap.add_argument("--grid", default="", help="also sweep query_cut x heap_factor, e.g. '5,10,20x0.7,0.8,0.9'")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-grid-1m", action="store_true",
+                    help="skip the 1M configuration's query_cut x heap_factor grid (run with the 8.8M default)")
     ap.add_argument("--no-k100", action="store_true",
                     help="skip the fixed k = 100 operating point (timed only in runs without --hf)")
     ap.add_argument("--lone-only", action="store_true",
@@ -1043,6 +1065,8 @@ def main():
         forms["serving"] = {name: [{"offered_qps": r_["offered_qps"], "sustained_qps": r_["sustained_qps"],
                                     "p50_ms": r_["p50_ms"], "p99_ms": r_["p99_ms"]} for r_ in rows]
                             for name, rows in serving.items()}
+    if args.workload == "msmarco-8.8M" and args.hf is None and not args.no_grid_1m:
+        forms["grid_1M"] = grid_1m_leg()
     out = {
         "metric": "QPS at Recall@10>=0.95 (1 GPU, 8.8M docs); p50/p99 query latency",
         "value": round(qps, 1),
