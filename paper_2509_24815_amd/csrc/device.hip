@@ -447,7 +447,7 @@ int build_copies(DeviceIndex* d, const HostIndex& h, const uint32_t* lists, uint
     HIP_TRY(hipMemcpy(groups.data(), d_groups, (size_t)J * 8, hipMemcpyDeviceToHost));
     // the longest prefix that fits
     const uint64_t nb = h.list_off[h.dim];
-    const uint64_t fixed = nb * 4 + 32 + 16;
+    const uint64_t fixed = nb * 4 + 32;  // the block map and the rows' padding
     std::vector<uint64_t> gbase(J + 1, 0);
     uint32_t keep = 0;
     for (uint32_t j = 0; j < J; ++j) {

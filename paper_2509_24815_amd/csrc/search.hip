@@ -79,6 +79,7 @@ struct SearchLds {
     uint32_t* wl_D;    // [kWideMaxCut] speculated blocks
     uint64_t* wl_S0;   // [kWideMaxCut] summary entries [S0, S1)
     uint64_t* wl_S1;   // [kWideMaxCut]
+    int64_t* wl_cb;    // [kWideMaxCut] copy_bias of the list
 };
 
 __host__ __device__ inline uint32_t r16u(uint64_t x) { return (uint32_t)((x + 15) & ~uint64_t(15)); }
@@ -372,13 +373,17 @@ __device__ inline void gather_and_score_t(const DevIdx& ix, const SearchLds<NT>&
     __syncthreads();
 }
 
-// Offset from a posting of block b (whose first posting is p0) to its
-// block-major copy, or kNoBias when the block's list has no copies.
+// Offset from a posting of a block to its block-major copy (bc = bcopy of
+// the block, p0 = its first posting), or kNoBias when its list has none.
 constexpr int64_t kNoBias = INT64_MIN;
-__device__ __forceinline__ int64_t copy_bias(const DevIdx& ix, uint32_t b, uint32_t p0) {
-    if (!ix.bcopy) return kNoBias;
-    const uint32_t c = __builtin_amdgcn_readfirstlane(ix.bcopy[b]);
-    return c == kNoCopy ? kNoBias : (int64_t)c - (int64_t)p0;
+__device__ __forceinline__ int64_t copy_bias(uint32_t bc, uint32_t p0) {
+    return bc == kNoCopy ? kNoBias : (int64_t)bc - (int64_t)p0;
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint64_t u = (uint64_t)x;
+    return (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32)) << 32) |
+                     (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)u));
 }
 
 // cbias: copy_bias of the window's list (the same for all its blocks).
@@ -605,6 +610,8 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
             L.wl_S0[ci] = ix.blk_sum_off[b0];
             L.wl_S1[ci] = ix.blk_sum_off[b1];
             L.wl_D[ci] = b1 > b0 ? a.wd_nspec[(size_t)qi * a.cmax + ci] : 0u;
+            const uint32_t bc = ix.bcopy && b1 > b0 ? ix.bcopy[b0] : kNoCopy;
+            L.wl_cb[ci] = copy_bias(bc, bc == kNoCopy ? 0u : ix.blk_post_off[b0]);
         }
         __syncthreads();
     }
@@ -627,16 +634,19 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
             if (a.prefix && tid == 0 && ci < a.prefix_stride) a.prefix[(size_t)qi * a.prefix_stride + ci] = 0;
             continue;
         }
-        const uint32_t ub0 = __builtin_amdgcn_readfirstlane(b0);
-        const int64_t cbias = copy_bias(ix, ub0, __builtin_amdgcn_readfirstlane(ix.blk_post_off[ub0]));
         // ---------------------------------------- a. summary scores
         uint64_t S0, S1;
+        int64_t cbias;  // block-major copies of the list's rows, if any
         if constexpr (WIDE) {
             S0 = L.wl_S0[ci];
             S1 = L.wl_S1[ci];
+            cbias = uniform64(L.wl_cb[ci]);
         } else {
             S0 = ix.blk_sum_off[b0];
             S1 = ix.blk_sum_off[b1];
+            const uint32_t ub0 = __builtin_amdgcn_readfirstlane(b0);
+            const uint32_t bc = ix.bcopy ? ix.bcopy[ub0] : kNoCopy;
+            cbias = copy_bias(bc, ix.blk_post_off[ub0]);
         }
         C.sum += S1 - S0;
         C.blocks += nb;
@@ -1094,6 +1104,7 @@ __global__ __launch_bounds__(NT, (LIST && NT == 256) ? 3 : 1) void k_search(Sear
         L.wl_D = (uint32_t*)carve(end, 4ull * kWideMaxCut);
         L.wl_S0 = (uint64_t*)carve(end, 8ull * kWideMaxCut);
         L.wl_S1 = (uint64_t*)carve(end, 8ull * kWideMaxCut);
+        L.wl_cb = (int64_t*)carve(end, 8ull * kWideMaxCut);
     }
     for (uint32_t i = tid; i < L.region_bytes / 16; i += NT) ((uint4*)L.region)[i] = make_uint4(0, 0, 0, 0);
     if (tid == 0) L.qv[0] = 0.0;
@@ -1388,7 +1399,7 @@ __global__ __launch_bounds__(kWideChunk) void k_wide_eval(SearchArgs a) {
         top.hn = 0;
         const uint32_t p0 = ix.blk_post_off[b], n = ix.blk_post_off[b + 1] - p0;
         const uint32_t c0 = c * NT, m = min((uint32_t)NT, n - c0);
-        const int64_t cbias = copy_bias(ix, b, p0);
+        const int64_t cbias = copy_bias(ix.bcopy ? __builtin_amdgcn_readfirstlane(ix.bcopy[b]) : kNoCopy, p0);
         if (tid == 0) { L.wst[0] = 0; L.wst[1] = m; L.wp0[0] = p0; }
         __syncthreads();
         if (in.u8mode)

@@ -89,7 +89,7 @@ constexpr uint32_t kWideMaxDepth = 64;  // largest speculation depth (blocks per
 constexpr uint32_t kWideMaxK = 64;      // largest k served by the wide schedule
 constexpr uint32_t kWideChunk = 256;    // documents per evaluation item (= its workgroup size)
 constexpr uint32_t kWideTinyBatch = 4;  // batches this small speculate twice the configured depth
-constexpr uint32_t kWideMetaBytes = 16 * kWideMaxDepth + 32 * kWideMaxCut;  // extra LDS of the wide traversal
+constexpr uint32_t kWideMetaBytes = 16 * kWideMaxDepth + 40 * kWideMaxCut;  // extra LDS of the wide traversal
 
 // Device buffers of the list-major schedule for up to nq queries.
 struct ListSched {
