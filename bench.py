@@ -342,10 +342,13 @@ def grid_1m_leg():
            "--steps", "5", "--warmup", "1"]
     log("[bench] 1M grid: " + " ".join(cmd[2:]))
     t0 = time.time()
-    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
-    if r.returncode != 0:
-        return {"error": f"exit status {r.returncode}"}
-    d = json.loads(r.stdout.strip().splitlines()[-1])
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
+        if r.returncode != 0:
+            return {"error": f"exit status {r.returncode}"}
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+    except (subprocess.TimeoutExpired, ValueError, IndexError) as e:
+        return {"error": f"{type(e).__name__}: {e}"}
     return {"qps": d["value"], "recall_at_10": d["config"]["recall_at_10"], "ms_per_step": d["ms_per_step"],
             "workload": d["config"]["workload"], "frac": d["roofline"]["frac"],
             "layout_frac": d["roofline"]["layout_frac"], "grid": d["config"]["grid"],
@@ -567,16 +570,26 @@ def main():
         before_ms, before_ids, before_sc = batch_ms()
         free, total = torch.cuda.mem_get_info()
         budget = max(0, int(free - args.hot_reserve_gb * 1e9))
+        t4 = time.time()
         n_cp, used = ix.copy_lists(order, budget)
+        copy_s = time.time() - t4
         after_ms, after_ids, after_sc = batch_ms()
+        # the timed batch's own evaluated blocks that lie in copied lists
+        _, _, b_pre, _, _, b_term = ix.search(qcsr, k, cut, hf_s, trace=True, prefix_stride=max(cut, 1))
+        torch.cuda.synchronize()
+        b_pre = b_pre.cpu().numpy().astype(np.uint16).astype(np.int64)
+        b_term = b_term.cpu().numpy().astype(np.int64)
         copied = np.zeros(qs.dim, dtype=bool)
         copied[order[:n_cp]] = True
         m = s_pre > 0
         cover = float(s_pre[m][copied[s_term[m]]].sum() / max(1, s_pre[m].sum()))
+        mb = b_pre > 0
+        cover_b = float(b_pre[mb][copied[b_term[mb]]].sum() / max(1, b_pre[mb].sum()))
         free, total = torch.cuda.mem_get_info()
         hot = {"lists_copied": n_cp, "lists_evaluated_by_sample": int(len(order)), "copies_gb": round(used / 1e9, 1),
                "sample_queries": args.hot_sample, "sample_heap_factor": hf_s,
-               "sample_blocks_in_copied_lists": round(cover, 4), "build_s": round(time.time() - t3, 1),
+               "sample_blocks_in_copied_lists": round(cover, 4), "batch_blocks_in_copied_lists": round(cover_b, 4),
+               "copy_s": round(copy_s, 2), "step_s": round(time.time() - t3, 1),
                "hbm_in_use_gb": round((total - free) / 1e9, 1),
                "batch_ms_rows_in_place": round(before_ms, 3), "batch_ms_with_copies": round(after_ms, 3),
                "same_results": bool(np.array_equal(before_ids, after_ids) and np.array_equal(before_sc, after_sc))}
