@@ -231,8 +231,10 @@ int seismic_index_upload(seismic_index* index, int device, uint32_t flags);
    max_bytes of device memory is copied (16-byte padded rows, 12 bytes of
    offsets per posting and 4 bytes per block of the index).  Blocks of
    other lists keep reading their rows in place; results never change.
-   *n_copied (nullable) = the length of that prefix, *bytes (nullable) =
-   the device memory taken.  EINVAL for a term id >= dim or one given
+   Lists without postings need no copies and count as copied.  *n_copied
+   (nullable) = the length of that prefix, *bytes (nullable) = the device
+   memory taken; when nothing fits, nothing is stored and a later call may
+   try again.  EINVAL for a term id >= dim or one given
    twice; ESTATE when the index is not resident or already has copies;
    ENOMEM when device memory runs out (nothing is kept).  Synchronous.  Not
    concurrently with searches on this index; launches made afterwards read
