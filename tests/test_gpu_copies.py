@@ -3,7 +3,8 @@ the C ABI.  With copies of some lists only — every other list of a sample
 batch's hot-list order, so that one query mixes lists read from copies and
 lists read in place — every schedule (query-major, list-major, wide)
 returns the oracle's results and the plain layout's bit for bit, blocks
-larger than a workgroup included.  Also: the byte budget keeps the longest
+larger than a workgroup included, and with the learned probe, the
+alpha_q cut and refinement.  Also: the byte budget keeps the longest
 prefix that fits, argument and state errors, copies of a device-built
 index, and freeing exact search's inverted index."""
 import numpy as np
@@ -11,7 +12,9 @@ import pytest
 
 import oracle
 import synth
+from oracle import mlp
 from paper_2509_24815_amd import Index, SeismicError, binding, hot_list_order
+from paper_2509_24815_amd import probe as P
 from tests.gpu_util import as_u32, compare_with_oracle, to_device_csr
 
 pytestmark = pytest.mark.gpu
@@ -23,12 +26,12 @@ def _log(msg):
     print(msg, flush=True)
 
 
-def _search(ix, q, k, cut, hf, schedule, window=8, threads=256):
+def _search(ix, q, k, cut, hf, schedule, window=8, threads=256, **kw):
     import torch
     ws = binding.seismic_workspace_create(ix.handle, max(q.n_rows, 1), max(k, 100))
     try:
         binding.seismic_workspace_set_config(ws, threads, 0, window, schedule)
-        out = ix.search(to_device_csr(q), k, cut, hf, trace=True, prefix_stride=cut, ws=ws)
+        out = ix.search(to_device_csr(q), k, cut, hf, trace=True, prefix_stride=cut, ws=ws, **kw)
         torch.cuda.synchronize()
         return [t.cpu().numpy() for t in out]
     finally:
@@ -74,6 +77,15 @@ def test_copies_of_some_lists_change_no_result():
     ref = oracle.Index(ix.serialize())
     ix.upload(0)
     before = [_search(ix, q, k, cut, hf, 0) for cut, hf, k in POINTS]
+    # the learned probe, the alpha_q cut and refinement read rows through the same gathers
+    rng = np.random.default_rng(3)
+    p = np.zeros(512, dtype=np.float32)
+    p[:mlp.N_USED] = rng.normal(0, 0.6, mlp.N_USED)
+    p[320:384] = np.abs(p[320:384])
+    w = mlp.float_to_bf16_bits(p)
+    ix.set_knn(rng.integers(0, docs.n_rows, (docs.n_rows, 8)).astype(np.uint32))
+    variants = [dict(probe=P.to_device(w), probe_tau=0.5), dict(query_mass=0.5, refine=True)]
+    before_v = [_search(ix, q, 10, 10, 0.8, 0, **kw) for kw in variants]
     lists = _every_other_hot(ix, synth.queries(400, seed=11), 10, 0.8)
     n, used = ix.copy_lists(lists, 1 << 62)
     _log(f"[copies] {n} of {len(lists)} lists copied, {used} bytes")
@@ -82,6 +94,11 @@ def test_copies_of_some_lists_change_no_result():
     with pytest.raises(SeismicError):  # copies exist already
         ix.copy_lists(lists[:1], 1 << 62)
     _check_all_schedules(ix, ref, q, before, POINTS)
+    for kw, base in zip(variants, before_v):
+        _log(f"[copies] {sorted(kw)}")
+        assert _same(_search(ix, q, 10, 10, 0.8, 0, **kw), base)
+        assert _same(_search(ix, q, 10, 10, 0.8, 1, **kw), base)
+        assert _same(_search(ix, q, 10, 10, 0.8, 2, window=16, threads=512, **kw), base)
 
 
 def test_copies_of_large_blocks():
