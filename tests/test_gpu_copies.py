@@ -152,6 +152,17 @@ def test_budget_errors_and_full_copies():
     assert 0 < n_half < n_all and used_half <= used_all // 2
     assert _same(_search(ix, qs, 10, 10, 0.8, 0), base)
     ix.close()
+    # lists without postings count as copied where they stand in the order
+    empty = np.setdiff1d(np.arange(dim), np.unique(docs.terms()))
+    assert len(empty) >= 2
+    ix = Index.build(docs, lam=500, beta=20, gamma=0.4, seed=6)
+    ix.upload(0)
+    n, used = ix.copy_lists([hot[0], hot[1]], 1)  # nothing fits
+    assert (n, used) == (0, 0) and ix.info()["on_device"] == 1
+    n, used = ix.copy_lists([empty[0], hot[0], empty[1], hot[1]], 1 << 62)
+    assert n == 4 and used > 0 and ix.info()["on_device"] == 3
+    assert _same(_search(ix, qs, 10, 10, 0.8, 0), base)
+    ix.close()
     # every list: the layout of SEISMIC_UPLOAD_BLOCK_ROWS
     ix = Index.build(docs, lam=500, beta=20, gamma=0.4, seed=6)
     ix.upload(0)
