@@ -349,9 +349,11 @@ def grid_1m_leg():
         d = json.loads(r.stdout.strip().splitlines()[-1])
     except (subprocess.TimeoutExpired, ValueError, IndexError) as e:
         return {"error": f"{type(e).__name__}: {e}"}
+    grid = [[p["query_cut"], p["hf"], p["recall"], round(p["qps"]), p["layout_frac"]] for p in d["config"]["grid"] or []]
     return {"qps": d["value"], "recall_at_10": d["config"]["recall_at_10"], "ms_per_step": d["ms_per_step"],
             "workload": d["config"]["workload"], "frac": d["roofline"]["frac"],
-            "layout_frac": d["roofline"]["layout_frac"], "grid": d["config"]["grid"],
+            "layout_frac": d["roofline"]["layout_frac"],
+            "grid_fields": ["query_cut", "heap_factor", "recall_at_10", "qps", "layout_frac"], "grid": grid,
             "seconds": round(time.time() - t0, 1)}
 
 
