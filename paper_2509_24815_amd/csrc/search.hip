@@ -610,8 +610,12 @@ __device__ __forceinline__ void run_lists(const SearchArgs& a, const SearchLds<N
             L.wl_S0[ci] = ix.blk_sum_off[b0];
             L.wl_S1[ci] = ix.blk_sum_off[b1];
             L.wl_D[ci] = b1 > b0 ? a.wd_nspec[(size_t)qi * a.cmax + ci] : 0u;
-            const uint32_t bc = ix.bcopy && b1 > b0 ? ix.bcopy[b0] : kNoCopy;
-            L.wl_cb[ci] = copy_bias(bc, bc == kNoCopy ? 0u : ix.blk_post_off[b0]);
+            uint32_t bc = kNoCopy, bp = 0;
+            if (ix.bcopy && b1 > b0) {  // both loads in one round
+                bc = ix.bcopy[b0];
+                bp = ix.blk_post_off[b0];
+            }
+            L.wl_cb[ci] = copy_bias(bc, bp);
         }
         __syncthreads();
     }
@@ -1263,10 +1267,11 @@ __global__ __launch_bounds__(NT) void k_wide_lists(SearchArgs a) {
                 // capacity and whose blocks' chunk sets fit one traversal
                 // window (chunks * k <= wd_nt candidates)
                 const uint32_t D0 = min(nb, nq <= kWideTinyBatch ? a.depth : a.depth_large);
-                uint32_t b = 0, n = 0, ch = 0;
+                uint32_t b = 0, n = 0, ch = 0, bc = kNoCopy;
                 if ((uint32_t)tid < D0) {
                     b = b0 + L.ord[tid];
                     n = ix.blk_post_off[b + 1] - ix.blk_post_off[b];
+                    if (ix.bcopy) bc = ix.bcopy[b];  // carried by the block's items
                     ch = (n + kWideChunk - 1) / kWideChunk;
                 }
                 uint32_t T;
@@ -1286,7 +1291,7 @@ __global__ __launch_bounds__(NT) void k_wide_lists(SearchArgs a) {
                     a.wd_first[slot0 + tid] = base + at;
                     a.wd_nnz[slot0 + tid] = 0;
                     a.wd_docs[slot0 + tid] = n;
-                    for (uint32_t j = 0; j < ch; ++j) a.wd_items[base + at + j] = make_uint4(b, j, slot0 + tid, 0);
+                    for (uint32_t j = 0; j < ch; ++j) a.wd_items[base + at + j] = make_uint4(b, j, slot0 + tid, bc);
                 } else if ((uint32_t)tid < D0) {
                     // items reserved for blocks past the prefix: no-ops
                     for (uint32_t j = 0; j < ch; ++j)
@@ -1399,7 +1404,7 @@ __global__ __launch_bounds__(kWideChunk) void k_wide_eval(SearchArgs a) {
         top.hn = 0;
         const uint32_t p0 = ix.blk_post_off[b], n = ix.blk_post_off[b + 1] - p0;
         const uint32_t c0 = c * NT, m = min((uint32_t)NT, n - c0);
-        const int64_t cbias = copy_bias(ix.bcopy ? __builtin_amdgcn_readfirstlane(ix.bcopy[b]) : kNoCopy, p0);
+        const int64_t cbias = copy_bias(__builtin_amdgcn_readfirstlane(it.w), p0);
         if (tid == 0) { L.wst[0] = 0; L.wst[1] = m; L.wp0[0] = p0; }
         __syncthreads();
         if (in.u8mode)

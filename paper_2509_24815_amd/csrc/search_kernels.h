@@ -67,7 +67,7 @@ struct SearchArgs {
     float* wd_r;            // [nq * cmax * sort_cap] summary scores in (r desc, block asc) order
     uint16_t* wd_ord;       // [nq * cmax * sort_cap] their block index within the list
     uint32_t* wd_nspec;     // [nq * cmax] speculated blocks of each cut list (a prefix of the order)
-    uint4* wd_items;        // [wd_icap] evaluation items: (block, chunk, result slot, 0)
+    uint4* wd_items;        // [wd_icap] evaluation items: (block, chunk, result slot, bcopy of the block)
     uint32_t wd_icap;       // item capacity
     uint32_t* wd_cnt;       // [4]: list queue, items requested, evaluation queue
     uint32_t* wd_first;     // [nq * cmax * depth] first item of each speculated block (its chunks follow)
